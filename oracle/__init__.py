@@ -1,0 +1,238 @@
+"""CPU oracle of the EPID transit Monte Carlo hot path -- TEST INFRASTRUCTURE.
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
+of ``bench.py`` may import this package.  The engine (``paper_2510_24154_amd``)
+never imports, links or calls it.
+
+This module only marshals a workload description (see
+``paper_2510_24154_amd.synth``) into the C structures of ``epid_oracle.h``; all
+arithmetic is in ``epid_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libepid_oracle.so")
+MAX_ELEM, MAX_MAT, MAX_LAYERS = 8, 16, 8
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, -O2)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-Wall", "-fPIC", "-shared", "-o", tmp,
+                               os.path.join(_HERE, "epid_oracle.c"), "-lm", "-lpthread"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Material(ct.Structure):
+    _fields_ = [("n_elem", ct.c_int), ("Z", ct.c_int * MAX_ELEM), ("A", ct.c_double * MAX_ELEM),
+                ("w", ct.c_double * MAX_ELEM), ("I_eV", ct.c_double)]
+
+
+class Config(ct.Structure):
+    _fields_ = [
+        ("coupled", ct.c_int), ("proc_mask", ct.c_uint32), ("pcut", ct.c_double), ("ecut", ct.c_double),
+        ("n_mat", ct.c_int), ("mat", Material * MAX_MAT),
+        ("nx", ct.c_int), ("ny", ct.c_int), ("nz", ct.c_int),
+        ("spacing", ct.c_double * 3), ("origin", ct.c_double * 3),
+        ("vox_mat", ct.POINTER(ct.c_uint8)), ("vox_rho", ct.POINTER(ct.c_double)),
+        ("n_layers", ct.c_int), ("layer_mat", ct.c_int * MAX_LAYERS),
+        ("layer_rho", ct.c_double * MAX_LAYERS), ("layer_t", ct.c_double * MAX_LAYERS),
+        ("scoring_layer", ct.c_int), ("front_z", ct.c_double),
+        ("npx_u", ct.c_int), ("npx_v", ct.c_int), ("pitch_u", ct.c_double), ("pitch_v", ct.c_double),
+        ("beam_kind", ct.c_int), ("src", ct.c_double * 3), ("iso_z", ct.c_double),
+        ("nbins", ct.c_int), ("edges", ct.POINTER(ct.c_double)), ("weights", ct.POINTER(ct.c_double)),
+        ("n_seg", ct.c_int), ("n_pairs", ct.c_int), ("leaf_w", ct.c_double), ("y0", ct.c_double),
+        ("a", ct.POINTER(ct.c_double)), ("b", ct.POINTER(ct.c_double)),
+        ("seg_hist", ct.POINTER(ct.c_uint64)),
+        ("n_phsp", ct.c_uint64), ("phsp", ct.POINTER(ct.c_double)),
+        ("seed", ct.c_uint64),
+    ]
+
+
+class Counters(ct.Structure):
+    _fields_ = [(n, ct.c_uint64) for n in (
+        "n_hist", "n_compton", "n_photo", "n_pair", "n_annih", "n_brems", "n_moller",
+        "e_steps", "voxel_visits", "photon_epid_entries", "unscattered_at_epid", "n_tally_deposits",
+        "n_first_collision")] + \
+        [(n, ct.c_double) for n in (
+            "e_first_collision", "e_track", "e_in", "e_dep_phantom", "e_dep_epid", "e_dep_other", "e_escaped", "e_rest_balance",
+            "max_ledger_resid")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                build()
+            L = ct.CDLL(LIB_PATH)
+            d, p = ct.c_double, ct.c_void_p
+            L.orc_run.argtypes = [ct.POINTER(Config), ct.c_uint64, ct.c_uint64, p, p, ct.POINTER(Counters)]
+            L.orc_run.restype = ct.c_int
+            L.orc_map_hu.argtypes = [p, ct.c_uint64, ct.c_int, p, p, ct.c_int, p, p, p, p]
+            L.orc_map_hu.restype = ct.c_int
+            for name, args in {
+                "orc_sigma_kn": [d], "orc_kn_sample": [d, d], "orc_kn_cdf": [d, d],
+                "orc_x0": [ct.POINTER(Material)], "orc_highland": [d, d, d],
+                "orc_lcol": [ct.POINTER(Material), d, ct.c_int, d],
+                "orc_lres": [ct.POINTER(Material), d, d, d],
+                "orc_sigma_moller": [ct.POINTER(Material), d, d],
+                "orc_sigma_brems": [ct.POINTER(Material), d, d],
+                "orc_moller_sample": [d, d, d],
+                "orc_range_diff": [ct.POINTER(Material), d, d, d, d],
+                "orc_range_inverse": [ct.POINTER(Material), d, d, d, d],
+            }.items():
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = d
+            L.orc_source.argtypes = [ct.POINTER(Config), ct.c_uint64, p]
+            L.orc_source.restype = ct.c_int
+            L.orc_photon_mu.argtypes = [ct.POINTER(Material), d, p]
+            L.orc_photon_mu.restype = None
+            L.orc_philox4x32_10.argtypes = [p, p, p]
+            L.orc_philox4x32_10.restype = None
+            _lib = L
+    return _lib
+
+
+def material(m: dict) -> Material:
+    s = Material()
+    s.n_elem = len(m["Z"])
+    for i, (z, a, w) in enumerate(zip(m["Z"], m["A"], m["w"])):
+        s.Z[i], s.A[i], s.w[i] = int(z), float(a), float(w)
+    s.I_eV = float(m["I_eV"])
+    return s
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def map_hu(hu, curve, ranges):
+    hu = np.ascontiguousarray(hu, dtype=np.int16)
+    ch = np.ascontiguousarray(curve["hu"], dtype=np.float64)
+    cr = np.ascontiguousarray(curve["rho"], dtype=np.float64)
+    up = np.ascontiguousarray(ranges["hu_upper"], dtype=np.float64)
+    mo = np.ascontiguousarray(ranges["mat"], dtype=np.int32)
+    om = np.empty(hu.size, dtype=np.uint8)
+    orho = np.empty(hu.size, dtype=np.float64)
+    rc = lib().orc_map_hu(hu.ctypes.data, hu.size, ch.size, ch.ctypes.data, cr.ctypes.data,
+                          mo.size, up.ctypes.data, mo.ctypes.data, om.ctypes.data, orho.ctypes.data)
+    if rc != 0:
+        raise ValueError("orc_map_hu failed")
+    return om, orho
+
+
+class Prepared:
+    """A workload marshalled into an oracle Config (keeps the arrays alive)."""
+
+    def __init__(self, cfg: dict, seed: int, phsp=None):
+        c = Config()
+        ph = cfg["physics"]
+        c.coupled, c.proc_mask, c.pcut, c.ecut = ph["coupled"], ph["proc_mask"], ph["pcut"], ph["ecut"]
+        mats = cfg["materials"]
+        c.n_mat = len(mats)
+        for i, m in enumerate(mats):
+            c.mat[i] = material(m)
+        P = cfg["phantom"]
+        c.nx, c.ny, c.nz = P["shape"]
+        for a in range(3):
+            c.spacing[a], c.origin[a] = P["spacing"][a], P["origin"][a]
+        if P["kind"] == "hu":
+            self.vm, self.vr = map_hu(P["hu"], P["curve"], P["ranges"])
+        else:
+            self.vm = np.ascontiguousarray(P["mat"], dtype=np.uint8)
+            self.vr = np.ascontiguousarray(P["rho"], dtype=np.float64)
+        c.vox_mat = self.vm.ctypes.data_as(ct.POINTER(ct.c_uint8))
+        c.vox_rho = _dptr(self.vr)
+        E = cfg["epid"]
+        c.n_layers = len(E["layers"])
+        for i, L in enumerate(E["layers"]):
+            c.layer_mat[i], c.layer_t[i], c.layer_rho[i] = L["mat"], L["t"], L["rho"]
+        c.scoring_layer, c.front_z = E["scoring"], E["front_z"]
+        c.npx_u, c.npx_v, c.pitch_u, c.pitch_v = E["npx_u"], E["npx_v"], E["pitch_u"], E["pitch_v"]
+        S = cfg["source"]
+        c.beam_kind = S["beam"]["kind"]
+        for a in range(3):
+            c.src[a] = S["beam"]["src"][a]
+        c.iso_z = S["beam"]["iso_z"]
+        self.edges = np.ascontiguousarray(S["edges"], dtype=np.float64)
+        self.weights = np.ascontiguousarray(S["weights"], dtype=np.float64)
+        c.nbins = self.weights.size
+        c.edges, c.weights = _dptr(self.edges), _dptr(self.weights)
+        ap = S["aperture"]
+        self.a = np.ascontiguousarray(ap["a"], dtype=np.float64)
+        self.b = np.ascontiguousarray(ap["b"], dtype=np.float64)
+        self.cnt = np.ascontiguousarray(ap["counts"], dtype=np.uint64)
+        c.n_seg, c.n_pairs = self.a.shape
+        c.leaf_w, c.y0 = ap["leaf_w"], ap["y0"]
+        c.a, c.b = _dptr(self.a), _dptr(self.b)
+        c.seg_hist = self.cnt.ctypes.data_as(ct.POINTER(ct.c_uint64))
+        if phsp is not None:
+            self.phsp = np.ascontiguousarray(phsp, dtype=np.float64).reshape(-1, 8)
+            c.n_phsp, c.phsp = self.phsp.shape[0], _dptr(self.phsp)
+        c.seed = int(seed)
+        self.c = c
+        self.npix = E["npx_u"] * E["npx_v"]
+        self.shape = (E["npx_v"], E["npx_u"])
+
+
+def source(cfg: dict, hs, seed: int = 1001, phsp=None):
+    """Source particles (x y z u v w E type) of the given history ids."""
+    P = Prepared(cfg, seed, phsp)
+    out = np.zeros((len(hs), 8))
+    for i, h in enumerate(hs):
+        lib().orc_source(ct.byref(P.c), int(h), out[i].ctypes.data)
+    return out
+
+
+def run(cfg: dict, n: int, seed: int = 1001, first: int = 0, threads: int = 1, phsp=None,
+        prepared: Prepared | None = None):
+    """Run histories [first, first+n) on `threads` threads over disjoint ranges.
+
+    Returns (mean, var_of_mean, sum, sum2, counters-dict); mean is MeV per history
+    per pixel, shape (npx_v, npx_u)."""
+    P = prepared or Prepared(cfg, seed, phsp)
+    L = lib()
+    threads = max(1, min(threads, n))
+    bounds = [first + (n * i) // threads for i in range(threads + 1)]
+    outs = [(np.zeros(P.npix), np.zeros(P.npix), Counters()) for _ in range(threads)]
+    errs = [0] * threads
+
+    def work(i):
+        s, s2, c = outs[i]
+        errs[i] = L.orc_run(ct.byref(P.c), bounds[i], bounds[i + 1] - bounds[i],
+                            s.ctypes.data, s2.ctypes.data, ct.byref(c))
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    if any(errs):
+        raise RuntimeError(f"orc_run failed: {errs}")
+    s = sum(o[0] for o in outs)
+    s2 = sum(o[1] for o in outs)
+    cnt = {}
+    for o in outs:
+        for k, v in o[2].as_dict().items():
+            cnt[k] = max(cnt.get(k, 0.0), v) if k == "max_ledger_resid" else cnt.get(k, 0) + v
+    mean = s / n
+    var = (s2 / n - mean * mean) / max(1, n - 1)
+    return mean.reshape(P.shape), np.maximum(var, 0).reshape(P.shape), s, s2, cnt

@@ -1,0 +1,139 @@
+/*
+ * epid_oracle.h -- CPU oracle for the EPID transit Monte Carlo hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product path
+ * (libepidmc.so and its Python binding) never links, imports or calls it.
+ *
+ * What it computes: for every EPID pixel, the expected energy deposited in the
+ * scoring layer per source history, D_ij, and the variance of its Monte Carlo
+ * estimate, by plain FP64 analog Monte Carlo:
+ *   - photons: photoelectric, Compton (Klein-Nishina) and pair production, the
+ *     three processes the paper models in the patient (Sec. 2.1.2), with cut-offs
+ *     of 10 keV for photons and 200 keV for electrons (Sec. 2.1.2);
+ *   - electrons: the Class II condensed-history scheme of Sec. 2.1.2 (discrete
+ *     hard collisions, continuous slowing down for soft ones), with the step
+ *     rules fixed in the readings listed in the design doc;
+ *   - geometry: a voxelised density matrix (Sec. 2.1.2) followed by a stack of
+ *     EPID layers (copper build-up, reflector, Gd2O2S phosphor, protective
+ *     layers; Sec. 2.1.3) with a 2D pixel grid in the scoring layer.
+ * Photons are tracked voxel by voxel (regular tracking, not delta tracking),
+ * cross sections are evaluated from their formulas at each energy (no tables),
+ * the Klein-Nishina and Moller samplers invert closed-form CDFs numerically, and
+ * the variance is accumulated history by history.
+ *
+ * Units: cm, MeV, g/cm^3.  The library is re-entrant: independent calls on
+ * disjoint history ranges may run in parallel threads and their sums are added.
+ */
+#ifndef EPID_ORACLE_H
+#define EPID_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_ELEM   8
+#define ORC_MAX_MAT    16
+#define ORC_MAX_LAYERS 8
+
+typedef struct {
+    int    n_elem;
+    int    Z[ORC_MAX_ELEM];
+    double A[ORC_MAX_ELEM];   /* g/mol */
+    double w[ORC_MAX_ELEM];   /* mass fractions, sum 1 */
+    double I_eV;              /* mean excitation energy */
+} orc_material;
+
+typedef struct {
+    /* physics */
+    int      coupled;         /* 0: KERMA (electrons deposit at birth), 1: coupled transport */
+    uint32_t proc_mask;       /* bit0 Compton, bit1 photoelectric, bit2 pair;
+                                 diagnostic switches: bit3 no hard electron events, bit4 no
+                                 multiple scattering */
+    double   pcut, ecut;      /* MeV: photon and electron transport cut-offs */
+    int      n_mat;
+    orc_material mat[ORC_MAX_MAT];
+    /* phantom: per-voxel material index and density, x fastest */
+    int      nx, ny, nz;
+    double   spacing[3];
+    double   origin[3];       /* minimum corner */
+    const uint8_t *vox_mat;
+    const double  *vox_rho;
+    /* EPID: contiguous layers starting at front_z, image centred on the z axis */
+    int      n_layers;
+    int      layer_mat[ORC_MAX_LAYERS];
+    double   layer_rho[ORC_MAX_LAYERS];
+    double   layer_t[ORC_MAX_LAYERS];
+    int      scoring_layer;
+    double   front_z;
+    int      npx_u, npx_v;    /* u along x (fast index), v along y */
+    double   pitch_u, pitch_v;
+    /* source */
+    int      beam_kind;       /* 0: parallel along +z from the plane z = src[2]; 1: point source at src */
+    double   src[3];
+    double   iso_z;           /* aperture plane of the point source */
+    int      nbins;           /* spectrum: nbins bins, edges[nbins+1], weights[nbins] */
+    const double *edges;
+    const double *weights;
+    int      n_seg, n_pairs;  /* MLC apertures: leaf pair k spans y in [y0+k*w, y0+(k+1)*w) */
+    double   leaf_w, y0;
+    const double *a, *b;      /* [n_seg][n_pairs] open x interval at the aperture plane */
+    const uint64_t *seg_hist; /* [n_seg] histories per segment (global ids are consecutive) */
+    uint64_t n_phsp;          /* >0: phase-space list replaces spectrum and aperture */
+    const double *phsp;       /* [n_phsp][8]: x y z u v w E type(0 photon, 1 e-, 2 e+) */
+    uint64_t seed;
+} orc_config;
+
+typedef struct {
+    uint64_t n_hist;
+    uint64_t n_compton, n_photo, n_pair, n_annih, n_brems, n_moller;
+    uint64_t e_steps, voxel_visits, photon_epid_entries;
+    uint64_t unscattered_at_epid;   /* source photons reaching the EPID front face unscattered */
+    uint64_t n_tally_deposits;
+    uint64_t n_first_collision;     /* first interactions of source photons in the scoring layer */
+    double   e_first_collision;     /* kinetic energy they set in motion */
+    double   e_track;               /* total electron path length (cm) */
+    double   e_in, e_dep_phantom, e_dep_epid, e_dep_other, e_escaped, e_rest_balance;
+    double   max_ledger_resid;      /* max over histories of |ledger residual| / E_in */
+} orc_counters;
+
+/* Return codes */
+#define ORC_OK        0
+#define ORC_E_ARG    -1
+#define ORC_E_LOOP   -2
+
+/* Transport histories [first, first+count).  sum[p] += e_h, sum2[p] += e_h^2 per history
+ * for every pixel p = v*npx_u + u (caller zeroes the arrays).  cnt is accumulated into. */
+int orc_run(const orc_config *cfg, uint64_t first, uint64_t count,
+            double *sum, double *sum2, orc_counters *cnt);
+
+/* source particle of history h: x y z u v w E type */
+int orc_source(const orc_config *cfg, uint64_t h, double out[8]);
+
+/* HU -> (material, density): piecewise-linear density curve (n_pts points, hu ascending,
+ * clamped outside) and material ranges: material mat_of[r] for HU < hu_upper[r], first match,
+ * the last range catching everything else. */
+int orc_map_hu(const int16_t *hu, uint64_t n, int n_pts, const double *curve_hu, const double *curve_rho,
+               int n_ranges, const double *hu_upper, const int *mat_of, uint8_t *out_mat, double *out_rho);
+
+/* ---- physics entry points exposed for pinning tests ---- */
+double orc_sigma_kn(double E);                       /* cm^2 per electron, closed form */
+void   orc_photon_mu(const orc_material *m, double E, double out[4]); /* cm^2/g: total, Compton, photo, pair */
+double orc_kn_sample(double E, double xi);            /* epsilon = E'/E by inverse CDF */
+double orc_kn_cdf(double E, double eps);              /* normalised CDF of epsilon */
+double orc_lcol(const orc_material *m, double T, int restricted, double wcut); /* MeV cm^2/g */
+double orc_lres(const orc_material *m, double T, double wcut, double kcut);   /* restricted total */
+double orc_sigma_moller(const orc_material *m, double T, double wcut);      /* cm^2/g */
+double orc_sigma_brems(const orc_material *m, double T, double kcut);       /* cm^2/g */
+double orc_moller_sample(double T, double wcut, double xi);                 /* W (MeV) */
+double orc_range_diff(const orc_material *m, double T_lo, double T_hi, double wcut, double kcut); /* g/cm^2 */
+double orc_range_inverse(const orc_material *m, double T0, double dR, double wcut, double kcut);
+double orc_x0(const orc_material *m);                 /* radiation length, g/cm^2 */
+double orc_highland(double T, double x_gcm2, double X0);
+void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

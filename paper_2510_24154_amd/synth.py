@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs for the EPID transit Monte Carlo workloads.
+
+This module only *describes* workloads: material compositions, geometry,
+HU phantoms, source spectra, MLC apertures and history counts.  It contains
+none of the transport arithmetic, so both the HIP engine and the CPU oracle
+can be fed from it without sharing any of the method's code.
+
+The paper's clinical inputs (VitalBeam phase space, patient CT, RTPLAN, the
+AS1200 layer specification, measured images; Sec. 2.1.1-2.1.3, 2.3) are not
+public.  Every workload here is a seeded synthetic stand-in with the shapes
+of the paper's setting: a point source 100 cm above the isocentre, the EPID
+scoring plane at 150 cm (Sec. 2.3.1-2.3.2), a copper build-up plate, a
+reflector, a Gd2O2S phosphor and a protective glass layer (Sec. 2.1.3).
+"""
+from __future__ import annotations
+
+import copy
+import numpy as np
+
+# --------------------------------------------------------------------------
+# materials: elemental mass fractions from the chemical formulas (or a fixed
+# soft-bone recipe), mean excitation energies as model inputs
+# --------------------------------------------------------------------------
+_H, _C, _N, _O = (1, 1.008), (6, 12.011), (7, 14.007), (8, 15.999)
+_MG, _SI, _P, _S = (12, 24.305), (14, 28.085), (15, 30.974), (16, 32.06)
+_AR, _CA, _CU, _GD = (18, 39.948), (20, 40.078), (29, 63.546), (64, 157.25)
+
+
+def _formula(parts):
+    """parts: list of ((Z, A), count) -> (Z list, A list, mass fractions)."""
+    mass = sum(el[1] * n for el, n in parts)
+    return ([el[0] for el, _ in parts], [el[1] for el, _ in parts],
+            [el[1] * n / mass for el, n in parts])
+
+
+def _mat(name, Z, A, w, I_eV, rho):
+    w = np.asarray(w, dtype=np.float64)
+    return {"name": name, "Z": list(Z), "A": list(A), "w": list(w / w.sum()),
+            "I_eV": float(I_eV), "rho": float(rho)}
+
+
+WATER = _mat("water", *_formula([(_H, 2), (_O, 1)]), 75.0, 1.0)
+LUNG = _mat("lung", *_formula([(_H, 2), (_O, 1)]), 75.0, 0.30)
+AIR = _mat("air", [7, 8, 18], [_N[1], _O[1], _AR[1]], [0.7553, 0.2318, 0.0129], 85.7, 0.0012)
+BONE = _mat("bone", [1, 6, 7, 8, 12, 15, 16, 20],
+            [_H[1], _C[1], _N[1], _O[1], _MG[1], _P[1], _S[1], _CA[1]],
+            [0.064, 0.278, 0.027, 0.410, 0.002, 0.070, 0.002, 0.147], 106.4, 1.60)
+COPPER = _mat("copper", [29], [_CU[1]], [1.0], 322.0, 8.96)
+PET = _mat("pet", *_formula([(_C, 10), (_H, 8), (_O, 4)]), 78.7, 1.38)
+GOS = _mat("gd2o2s", *_formula([(_GD, 2), (_O, 2), (_S, 1)]), 400.0, 7.44)
+GLASS = _mat("glass", *_formula([(_SI, 1), (_O, 2)]), 139.2, 2.50)
+
+# default HU -> density curve (piecewise linear) and HU -> material ranges
+HU_CURVE = {"hu": [-1000.0, 0.0, 3000.0], "rho": [0.0, 1.0, 2.8]}
+HU_RANGES = {"hu_upper": [-950.0, -200.0, 300.0], "mat": [0, 1, 2, 3]}  # air, lung, water, bone
+
+PHOTON_CUT = 0.010   # MeV (Sec. 2.1.2)
+ELECTRON_CUT = 0.200  # MeV (Sec. 2.1.2)
+
+
+def _epid(layers, scoring, front_z, npx_u, npx_v, pitch):
+    return {"layers": layers, "scoring": scoring, "front_z": float(front_z),
+            "npx_u": int(npx_u), "npx_v": int(npx_v), "pitch_u": float(pitch), "pitch_v": float(pitch)}
+
+
+def _open_field(half_x, half_y, leaf_w=0.5):
+    n = int(round(2 * half_y / leaf_w))
+    return {"n_pairs": n, "leaf_w": leaf_w, "y0": -half_y,
+            "a": np.full((1, n), -half_x), "b": np.full((1, n), half_x),
+            "counts": np.array([0], dtype=np.uint64)}
+
+
+# --------------------------------------------------------------------------
+# workload 1: photon-only KERMA, 2 MeV parallel beam, 20 cm water box
+# --------------------------------------------------------------------------
+def kerma_water(nvox=100, npx=128, spacing=None, pitch=None):
+    """2 MeV mono-energetic 10x10 cm parallel beam onto a 20 cm water cube of
+    2 mm voxels; a 2 mm Cu + 0.3 mm Gd2O2S + 1 mm glass stack 50 cm behind the
+    exit face; 128x128 image of 2 mm pixels in the phosphor; Compton and
+    photoelectric only, electrons deposited where they are set in motion."""
+    spacing = 20.0 / nvox if spacing is None else spacing
+    pitch = 25.6 / npx if pitch is None else pitch
+    n = nvox
+    return {
+        "name": "kerma_water",
+        "materials": [copy.deepcopy(m) for m in (WATER, COPPER, GOS, GLASS)],
+        "physics": {"coupled": 0, "proc_mask": 0b011, "pcut": PHOTON_CUT, "ecut": ELECTRON_CUT},
+        "phantom": {"kind": "direct", "shape": (n, n, n), "spacing": (spacing,) * 3,
+                    "origin": (-10.0, -10.0, 0.0),
+                    "mat": np.zeros(n * n * n, dtype=np.uint8),
+                    "rho": np.ones(n * n * n, dtype=np.float32)},
+        "epid": _epid([{"mat": 1, "t": 0.2, "rho": 8.96},
+                       {"mat": 2, "t": 0.03, "rho": 7.44},
+                       {"mat": 3, "t": 0.1, "rho": 2.5}], 1, 70.0, npx, npx, pitch),
+        "source": {"beam": {"kind": 0, "src": (0.0, 0.0, 0.0), "iso_z": 0.0},
+                   "edges": np.array([2.0, 2.0]), "weights": np.array([1.0]),
+                   "aperture": _open_field(5.0, 5.0)},
+    }
+
+
+# --------------------------------------------------------------------------
+# workload 2: coupled transport, 6 MV-like spectrum, heterogeneous phantom
+# --------------------------------------------------------------------------
+def ellipsoid_list(seed=2):
+    """Seeded lung (HU -700) and bone (HU +1000) ellipsoids in a 51.2 x 51.2 x
+    25.6 cm phantom centred on the isocentre (z = 100 cm)."""
+    rng = np.random.default_rng(seed)
+    ell = []
+    for _ in range(2):
+        ax = rng.uniform(3, 7, 2).tolist() + [rng.uniform(3, 8)]
+        c = rng.uniform(-8, 8, 2).tolist() + [100.0 + rng.uniform(-6.4, 6.4)]
+        ell.append({"hu": -700, "c": c, "ax": ax})
+    for _ in range(4):
+        ax = rng.uniform(0.5, 2.0, 3).tolist()
+        c = rng.uniform(-8, 8, 2).tolist() + [100.0 + rng.uniform(-6.4, 6.4)]
+        ell.append({"hu": 1000, "c": c, "ax": ax})
+    return ell
+
+
+def hu_grid(shape, spacing, origin, ellipsoids, background=0):
+    """int16 HU grid, x fastest; a voxel takes the HU of the last ellipsoid containing its centre."""
+    nx, ny, nz = shape
+    xs = origin[0] + (np.arange(nx) + 0.5) * spacing[0]
+    ys = origin[1] + (np.arange(ny) + 0.5) * spacing[1]
+    zs = origin[2] + (np.arange(nz) + 0.5) * spacing[2]
+    hu = np.full((nz, ny, nx), background, dtype=np.int16)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    for e in ellipsoids:
+        (cx, cy, cz), (ax, ay, az) = e["c"], e["ax"]
+        inside = ((X - cx) / ax) ** 2 + ((Y - cy) / ay) ** 2 + ((Z - cz) / az) ** 2 <= 1.0
+        hu[inside] = e["hu"]
+    return hu.reshape(-1)
+
+
+def thin_target_spectrum(seed=3, e0=6.0, lo=0.1, hi=6.0, width=0.05):
+    """Binned thin-target bremsstrahlung shape (1/k)(1 - k/E0) for E0 = 6 MeV
+    electrons, integrated over 0.05 MeV bins from 0.1 to 6.0 MeV (118 bins),
+    with a seeded per-bin jitter U(0.95, 1.05) and renormalisation."""
+    nb = int(round((hi - lo) / width))
+    edges = lo + width * np.arange(nb + 1)
+    k1, k2 = edges[:-1], edges[1:]
+    w = np.log(k2 / k1) - (k2 - k1) / e0
+    w *= np.random.default_rng(seed).uniform(0.95, 1.05, nb)
+    return edges, w / w.sum()
+
+
+def coupled_hetero(shape=(256, 256, 128), spacing=0.2, npx=(768, 1024), pitch=0.039,
+                   phantom_seed=2, spectrum_seed=3):
+    """Coupled photon-electron transport: seeded 6 MV-like spectrum, 10x10 cm
+    field at the isocentre from a point source 100 cm above it, heterogeneous
+    phantom of 2 mm voxels (water, lung and bone ellipsoids), 4-layer EPID with
+    its phosphor mid-plane at 150 cm, 1024x768 image of 0.39 mm pixels."""
+    nx, ny, nz = shape
+    sp = (float(spacing),) * 3 if np.isscalar(spacing) else tuple(float(s) for s in spacing)
+    origin = (-0.5 * nx * sp[0], -0.5 * ny * sp[1], 100.0 - 0.5 * nz * sp[2])
+    edges, w = thin_target_spectrum(spectrum_seed)
+    layers = [{"mat": 4, "t": 0.2, "rho": 8.96}, {"mat": 5, "t": 0.02, "rho": 1.38},
+              {"mat": 6, "t": 0.03, "rho": 7.44}, {"mat": 7, "t": 0.1, "rho": 2.5}]
+    front = 150.0 - 0.015 - 0.02 - 0.2
+    return {
+        "name": "coupled_hetero",
+        "materials": [copy.deepcopy(m) for m in (AIR, LUNG, WATER, BONE, COPPER, PET, GOS, GLASS)],
+        "physics": {"coupled": 1, "proc_mask": 0b111, "pcut": PHOTON_CUT, "ecut": ELECTRON_CUT},
+        "phantom": {"kind": "hu", "shape": (nx, ny, nz), "spacing": sp, "origin": origin,
+                    "hu": hu_grid((nx, ny, nz), sp, origin, ellipsoid_list(phantom_seed)),
+                    "curve": copy.deepcopy(HU_CURVE), "ranges": copy.deepcopy(HU_RANGES)},
+        "epid": _epid(layers, 2, front, npx[0], npx[1], pitch),
+        "source": {"beam": {"kind": 1, "src": (0.0, 0.0, 0.0), "iso_z": 100.0},
+                   "edges": edges, "weights": w, "aperture": _open_field(5.0, 5.0)},
+    }
+
+
+def coupled_hetero_small():
+    """The coupled workload on a coarse grid the oracle finishes quickly: same
+    physical extents, 8 mm voxels, 96x128 image of 3.12 mm pixels."""
+    return coupled_hetero(shape=(64, 64, 32), spacing=0.8, npx=(96, 128), pitch=0.312)
+
+
+# --------------------------------------------------------------------------
+# workload 3: IMRT-like field of 40 MLC segments with uneven history counts
+# --------------------------------------------------------------------------
+def mlc_segments(n_seg=40, n_pairs=60, leaf_w=0.5, total=300_000_000,
+                 aperture_seed=4, count_seed=5, lo=1_000_000, hi=50_000_000):
+    ra = np.random.default_rng(aperture_seed)
+    g = ra.uniform(0, 10, (n_seg, n_pairs))
+    c = ra.uniform(-5, 5, (n_seg, n_pairs))
+    a, b = c - g / 2, c + g / 2
+    rc = np.random.default_rng(count_seed)
+    w = np.exp(rc.uniform(np.log(lo), np.log(hi), n_seg))
+    n = np.clip(np.round(total * w / w.sum()), lo, hi).astype(np.int64)
+    for _ in range(100):   # push the residual onto the unclamped segments
+        r = total - int(n.sum())
+        if r == 0:
+            break
+        free = np.where((n > lo) & (n < hi))[0] if r < 0 else np.where(n < hi)[0]
+        step = np.sign(r) * np.maximum(1, np.abs(r) // max(1, len(free)))
+        for i in free:
+            if r == 0:
+                break
+            d = int(np.clip(n[i] + step, lo, hi) - n[i])
+            d = d if abs(d) <= abs(r) else r
+            n[i] += d
+            r -= d
+    return {"n_pairs": n_pairs, "leaf_w": leaf_w, "y0": -0.5 * n_pairs * leaf_w,
+            "a": a, "b": b, "counts": n.astype(np.uint64)}
+
+
+def imrt_field(total=300_000_000, **kw):
+    cfg = coupled_hetero(**kw)
+    cfg["name"] = "imrt40"
+    cfg["source"]["aperture"] = mlc_segments(total=total)
+    return cfg
+
+
+def with_histories_scaled(cfg, total):
+    """Copy of a multi-segment workload with every segment count scaled to sum to `total`."""
+    cfg = copy.deepcopy(cfg)
+    ap = cfg["source"]["aperture"]
+    c = ap["counts"].astype(np.float64)
+    n = np.maximum(1, np.floor(c * total / c.sum())).astype(np.int64)
+    n[np.argmax(n)] += total - int(n.sum())
+    ap["counts"] = n.astype(np.uint64)
+    return cfg
