@@ -1,0 +1,148 @@
+"""Benchmark of the EPID transit Monte Carlo hot path on one MI355X.
+
+Workload (one "step"): the coupled photon-electron configuration -- 1e8 histories
+from a seeded 6 MV-like spectrum through a 256x256x128 phantom of 2 mm voxels (HU
+from seeded water/lung/bone ellipsoids, 3 materials) into a 4-layer EPID with a
+1024x768 image of 0.39 mm pixels, FP32 transport, FP64 tally, 64 variance batches.
+Inputs are resident in HBM before timing; the timed region is K full runs.
+
+Prints one JSON line: histories/s (whole job), the extrapolated time to 1% mean
+relative uncertainty, the roofline figure of the dominant kernel (live HIP-event
+durations from the engine's profiling mode), and the oracle timed on host cores
+over a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HISTORIES = 100_000_000
+BATCHES = 64
+CHUNK = 1 << 25
+# peak plain-ALU issue rate of MI355X: 256 CUs x 64 lanes x 2.4 GHz (one VALU op per lane per
+# clock; FMA and packed FP32 doubling excluded because the hot path is not FMA-bound)
+ALU_PEAK_OPS = 256 * 64 * 2.4e9
+# algorithmic VALU lane-operations per unit of work ("Roofline")
+OPS_PER_UNIT = {"electron_step": 310, "woodcock_step": 120, "epid_photon_step": 130}
+KIND = ["photon_phantom", "electron_phantom", "photon_epid", "electron_epid"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--histories", type=int, default=HISTORIES)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; a run on N GPUs would shard histories "
+                                   "by id and all-reduce the tallies (see DESIGN.md), which is not built"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2510_24154_amd as E
+    from paper_2510_24154_amd import synth
+
+    cfg = synth.coupled_hetero()
+    eng = E.Engine(0, seed=1).configure(cfg, batches=BATCHES, max_chunk=min(CHUNK, a.histories))
+    eng.bind()
+    eng.set_profiling(True)
+    h = 0
+    for _ in range(a.warmup):
+        eng.run(a.histories, first=h)
+        h += a.histories
+    eng.reset()
+    torch.cuda.synchronize()
+    first = h
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        eng.run(a.histories, first=h)
+        h += a.histories
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = a.steps * a.histories
+    sb = eng.sigma_bar(0.5)
+    c = eng.counters()
+    value = n / dt
+    t1 = dt * (sb / 0.01) ** 2 if sb > 0 else None
+
+    # roofline of the dominant kernel: algorithmic lane-ops per launch / average launch time
+    units = {1: c["e_steps_phantom"], 0: c["woodcock_steps"], 2: c["epid_photon_steps"], 3: c["e_steps_epid"]}
+    per = {1: OPS_PER_UNIT["electron_step"], 0: OPS_PER_UNIT["woodcock_step"], 2: OPS_PER_UNIT["epid_photon_step"],
+           3: OPS_PER_UNIT["electron_step"]}
+    dom = max(range(4), key=lambda k: c["kernel_ms"][k])
+    launches = max(1, c["kernel_launches"][dom])
+    avg_s = c["kernel_ms"][dom] / 1e3 / launches
+    ops_per_launch = units[dom] * per[dom] / launches
+    achieved = ops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    roof = {"bound": "alu", "kernel": "k_electron<phantom>" if dom == 1 else KIND[dom],
+            "achieved": round(achieved, 3), "peak": round(ALU_PEAK_OPS / 1e12, 3), "unit": "Tlane-op/s",
+            "frac": round(achieved * 1e12 / ALU_PEAK_OPS, 4), "traffic": None,
+            "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches,
+            "unit_of_work": "electron condensed-history step" if dom in (1, 3) else KIND[dom],
+            "units_per_launch": round(units[dom] / launches), "ops_per_unit": per[dom],
+            "lane_utilisation": round(c["lane_iters"][dom] / max(1, c["wave_iters"][dom]), 4)}
+
+    if a.calib_copy:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        ns = a.cpu_sample
+        tc = time.perf_counter()
+        oracle.run(cfg, ns, seed=1001, first=0, threads=threads)
+        tcd = time.perf_counter() - tc
+        cpu = {"value": round(ns / tcd, 1), "unit": "histories/s", "cores": threads, "kind": "oracle",
+               "sample": f"{ns} histories of the same workload (ids 0..{ns - 1}), {tcd:.1f} s wall on {threads} threads"}
+
+    out = {
+        "metric": "photon histories/s (coupled transport to a 1% EPID image)",
+        "value": round(value, 1),
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(dt / a.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "coupled 6MV-like spectrum, 256x256x128 HU phantom (water/lung/bone), "
+                               "4-layer EPID 1024x768 @0.39 mm, 1e8 histories per step",
+                   "histories_per_step": a.histories, "batches": BATCHES, "tally": "fp64",
+                   "first_history": first},
+        "s_to_1pct_extrapolated": round(t1, 2) if t1 else None,
+        "sigma_bar_at_N": round(sb, 5),
+        "N_for_sigma_bar": n,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "counters": {k: c[k] for k in ("woodcock_steps", "e_steps_phantom", "e_steps_epid", "epid_photon_steps",
+                                       "tally_deposits", "launches", "kernel_ms", "kernel_launches",
+                                       "queue_items", "lane_iters", "wave_iters")},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

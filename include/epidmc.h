@@ -1,0 +1,252 @@
+/*
+ * epidmc.h -- C ABI of the MI355X (gfx950) EPID transit Monte Carlo engine.
+ *
+ * The engine transports photon histories and the electrons they set in motion
+ * through a voxelised CT phantom and a multi-layer EPID, and tallies the energy
+ * deposited in the EPID scoring layer into a 2D image with a per-pixel variance.
+ * This is the patient and EPID part of the three-zone scheme of the paper
+ * (Sec. 2.1, Fig. 1): particles leaving the treatment head (the second phase
+ * space, Sec. 2.1.1) enter a density matrix derived from CT numbers (Sec. 2.1.2),
+ * where photoelectric absorption, Compton scattering and pair production are
+ * modelled for photons and a Class II condensed-history scheme for electrons,
+ * with 10 keV and 200 keV cut-offs (Sec. 2.1.2); the particles crossing the exit
+ * plane (the third phase space) continue into a stack of copper, reflector,
+ * Gd2O2S and protective layers whose dose is scored on a pixel grid
+ * (Sec. 2.1.3, Sec. 2.3.3).
+ *
+ * Units: cm, MeV, g/cm^3.  Coordinates: a right-handed frame whose z axis is the
+ * beam axis; the EPID image is centred on x = y = 0, its u index runs along x and
+ * its v index along y; images are row-major [v][u].
+ *
+ * Ownership and memory: the caller owns every host array passed in; set_* calls
+ * validate and copy them into the context (host side) and return.  The engine
+ * allocates no device memory: the caller queries epidmc_workspace_size() and
+ * binds a device buffer of at least that size with epidmc_bind_workspace(),
+ * which uploads the model.  Any set_* call after binding un-binds the context
+ * (EPIDMC_E_NOT_READY) until the workspace is bound again.  Device pointers
+ * (workspace, output images) are plain hipMalloc'd addresses, e.g. from PyTorch
+ * tensors; streams are hipStream_t passed as void* (NULL = default stream).
+ *
+ * Errors: every call returns an epidmc_status; no exception crosses the ABI.
+ * epidmc_last_error() returns a message for the last failed call on a context.
+ * Device-side faults (queue overflow, step-limit, NaN energy, fixed-point
+ * overflow) are latched in a device error word and reported as
+ * EPIDMC_E_OVERFLOW / EPIDMC_E_NAN by the next call that synchronises (run,
+ * run_until, get_counters).  A context is not thread safe; use one per thread.
+ */
+#ifndef EPIDMC_H
+#define EPIDMC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct epidmc_ctx epidmc_ctx;
+
+typedef enum {
+    EPIDMC_OK = 0,
+    EPIDMC_E_ARG = -1,        /* invalid argument value */
+    EPIDMC_E_SHAPE = -2,      /* inconsistent sizes */
+    EPIDMC_E_RANGE = -3,      /* value outside the supported range */
+    EPIDMC_E_NOT_READY = -4,  /* model incomplete or workspace not bound */
+    EPIDMC_E_WORKSPACE = -5,  /* workspace too small or misaligned */
+    EPIDMC_E_DEVICE = -6,     /* HIP runtime error */
+    EPIDMC_E_OVERFLOW = -7,   /* particle queue, step limit or fixed-point overflow */
+    EPIDMC_E_NAN = -8         /* non-finite energy or position met on the device */
+} epidmc_status;
+
+typedef enum {
+    EPIDMC_TALLY_FP64 = 0,     /* FP64 atomic adds into the image */
+    EPIDMC_TALLY_FIXED64 = 1,  /* int64 fixed point, quantum 2^-32 MeV: bit-reproducible */
+    EPIDMC_TALLY_KAHAN32 = 2   /* deposit records reduced per tile with Kahan-compensated FP32 */
+} epidmc_tally_mode;
+
+typedef enum {
+    EPIDMC_PHYS_KERMA = 0,    /* electrons deposit their kinetic energy where they are set in motion */
+    EPIDMC_PHYS_COUPLED = 1   /* electrons are transported by condensed history */
+} epidmc_phys_mode;
+
+/* process mask bits */
+#define EPIDMC_PROC_COMPTON  1u
+#define EPIDMC_PROC_PHOTO    2u
+#define EPIDMC_PROC_PAIR     4u
+#define EPIDMC_DIAG_NO_HARD  8u    /* diagnostic: no discrete electron events */
+#define EPIDMC_DIAG_NO_MSC  16u    /* diagnostic: no multiple scattering */
+
+#define EPIDMC_MAX_ELEM 8
+#define EPIDMC_MAX_MATERIALS 16
+#define EPIDMC_MAX_PHANTOM_MATERIALS 4   /* materials present in one phantom */
+#define EPIDMC_MAX_LAYERS 6
+#define EPIDMC_MAX_SEGMENTS 256
+#define EPIDMC_MAX_BATCH_SLOTS 128
+
+/* A material: elemental composition by mass fraction and mean excitation energy. */
+typedef struct {
+    int    n_elem;
+    int    Z[EPIDMC_MAX_ELEM];
+    double A[EPIDMC_MAX_ELEM];   /* g/mol */
+    double w[EPIDMC_MAX_ELEM];   /* mass fractions (normalised by the engine) */
+    double I_eV;                 /* mean excitation energy */
+} epidmc_material;
+
+/* CT number -> density (piecewise linear over n_points ascending HU, clamped outside)
+ * and CT number -> material (material[r] for HU < hu_upper[r], first match; the last
+ * range, r = n_ranges-1, takes everything else and its hu_upper is ignored).  This is the
+ * HU-to-density conversion of Sec. 2.1.2, with the curve supplied by the caller. */
+typedef struct {
+    int           n_points;
+    const double *hu;
+    const double *rho;
+    int           n_ranges;
+    const double *hu_upper;
+    const int    *material;
+} epidmc_hu_curve;
+
+/* One EPID layer: material index, thickness along z (cm), density (g/cm^3). */
+typedef struct {
+    int   material;
+    float thickness;
+    float density;
+} epidmc_layer;
+
+/* Beam: kind 0 = parallel beam along +z starting on the plane z = src[2], with the
+ * aperture defining (x, y) on that plane; kind 1 = point source at src aimed at a
+ * point drawn uniformly over the open aperture area on the plane z = iso_z. */
+typedef struct {
+    int   kind;
+    float src[3];
+    float iso_z;
+} epidmc_beam;
+
+/* A phase-space particle (global frame): type 0 photon, 1 electron. */
+typedef struct {
+    float x, y, z, u, v, w, E;
+    int   type;
+} epidmc_particle;
+
+typedef struct {
+    uint64_t histories;            /* histories transported since the last reset */
+    uint64_t n_compton, n_photo, n_pair, n_annih, n_brems, n_moller;
+    uint64_t woodcock_steps;       /* real + virtual delta-tracking steps in the phantom */
+    uint64_t epid_photon_steps;    /* photon flights in the EPID slabs */
+    uint64_t e_steps_phantom, e_steps_epid;
+    uint64_t photon_epid_entries, unscattered_at_epid;
+    uint64_t tally_deposits;
+    uint64_t queue_items[4];       /* particles consumed per queue: photon-phantom,
+                                      electron-phantom, photon-EPID, electron-EPID */
+    uint64_t lane_iters[4];        /* per queue kernel: sum over wave iterations of active lanes */
+    uint64_t wave_iters[4];        /* per queue kernel: wave iterations x 64 */
+    uint64_t launches;             /* transport kernel launches */
+    uint64_t queue_peak;           /* largest queue fill seen */
+    uint32_t error_word;           /* latched device error bits */
+    double   max_ledger_resid;     /* diagnostics on: max per-history |E_in - deposited - escaped
+                                      - net rest energy| / E_in */
+    double   e_in, e_deposited, e_escaped;
+    double   kernel_ms[4];         /* profiling on: summed HIP-event durations of the transport
+                                      kernels per queue kind (same order as queue_items) */
+    uint64_t kernel_launches[4];
+} epidmc_counters;
+
+/* ---- lifetime ---------------------------------------------------------------- */
+/* Create a context on HIP device `device`; `seed` keys the counter-based random
+ * streams (Philox4x32-10, one stream per history and particle). */
+epidmc_status epidmc_create(epidmc_ctx **out, int device, uint64_t seed);
+epidmc_status epidmc_destroy(epidmc_ctx *c);
+/* Message of the last failed call; valid until the next call on c. */
+const char *epidmc_last_error(const epidmc_ctx *c);
+
+/* ---- model ------------------------------------------------------------------- */
+/* Material table; phantom and EPID layers refer to materials by index. */
+epidmc_status epidmc_set_materials(epidmc_ctx *c, const epidmc_material *m, int n_materials);
+/* Physics: transport mode, process mask (EPIDMC_PROC_* | EPIDMC_DIAG_*), cut-offs in
+ * MeV (the paper's 0.010 photon and 0.200 electron cut-offs, Sec. 2.1.2).  Kinetic
+ * energies below a cut-off are deposited on the spot. */
+epidmc_status epidmc_set_physics(epidmc_ctx *c, epidmc_phys_mode mode, uint32_t process_mask,
+                                 float photon_cut_MeV, float electron_cut_MeV);
+/* Phantom from CT numbers, x fastest: hu[(k*ny + j)*nx + i]; spacing and origin (the
+ * minimum corner) in cm.  The curve maps HU to (material, density) (Sec. 2.1.2). */
+epidmc_status epidmc_set_phantom_hu(epidmc_ctx *c, const int16_t *hu, int nx, int ny, int nz,
+                                    const float spacing[3], const float origin[3],
+                                    const epidmc_hu_curve *curve);
+/* Phantom from per-voxel material index and density. */
+epidmc_status epidmc_set_phantom_direct(epidmc_ctx *c, const uint8_t *mat, const float *rho,
+                                        int nx, int ny, int nz, const float spacing[3],
+                                        const float origin[3]);
+/* EPID: contiguous layers from z = front_z downstream (Sec. 2.1.3), the index of the
+ * scoring layer, and the image: npx_u x npx_v pixels of pitch_u x pitch_v centred on
+ * the axis (Sec. 2.3.3).  The lateral extent of every layer is the image area. */
+epidmc_status epidmc_set_epid(epidmc_ctx *c, const epidmc_layer *layers, int n_layers, int scoring_layer,
+                              float front_z, int npx_u, int npx_v, float pitch_u, float pitch_v);
+/* Source spectrum: nbins bins with edges[nbins+1] (non-decreasing, MeV) and
+ * non-negative weights[nbins]; energy uniform within the chosen bin (a zero-width bin is
+ * a line).  Replaces any phase-space list. */
+epidmc_status epidmc_set_source_spectrum(epidmc_ctx *c, const float *edges_MeV, const float *weights,
+                                         int nbins, const epidmc_beam *beam);
+/* Phase-space list (the particles after the collimators, Sec. 2.1.1): history h
+ * starts from particle h mod n.  Replaces the spectrum and aperture sampling. */
+epidmc_status epidmc_set_source_phsp(epidmc_ctx *c, const epidmc_particle *p, uint64_t n);
+/* MLC apertures on the beam's aperture plane: leaf pair k of segment s spans y in
+ * [y0 + k*w, y0 + (k+1)*w) and is open for x in [a[s*n_pairs+k], b[s*n_pairs+k]]
+ * (the apertures of Sec. 2.1.1, taken from the plan).  Global history ids are assigned
+ * to segments consecutively by n_hist[s]; with one segment n_hist is ignored. */
+epidmc_status epidmc_set_segments(epidmc_ctx *c, int n_segments, int n_pairs, float leaf_width, float y0,
+                                  const float *a, const float *b, const uint64_t *n_hist);
+/* Tally: mode, variance batches per run call (>= 2; 64 or more recommended), and the
+ * largest number of histories processed together (sets queue capacities). */
+epidmc_status epidmc_set_tally(epidmc_ctx *c, epidmc_tally_mode mode, int batches_per_run,
+                               uint64_t max_chunk_histories);
+/* Diagnostics: when on, every history's energy ledger is kept on the device and checked. */
+epidmc_status epidmc_set_diagnostics(epidmc_ctx *c, int enable);
+/* Profiling: when on, every transport launch is bracketed by HIP events on the run stream
+ * and the durations are summed into epidmc_counters.kernel_ms. */
+epidmc_status epidmc_set_profiling(epidmc_ctx *c, int enable);
+
+/* ---- memory ------------------------------------------------------------------ */
+epidmc_status epidmc_workspace_size(epidmc_ctx *c, size_t *bytes);
+/* Bind caller-owned device memory (256-byte aligned, >= workspace_size bytes) and
+ * upload the model on `stream`.  Clears the tally. */
+epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev_ptr, size_t bytes, void *stream);
+
+/* ---- run --------------------------------------------------------------------- */
+/* Transport histories [first_history, first_history + n_histories) on `stream`, split
+ * into the configured number of variance batches, and fold them into the tally.
+ * Returns after the work has completed.  first + n must not exceed 2^32. */
+epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first_history, uint64_t n_histories, void *stream);
+/* Run chunks of `step_histories` from history `first_history` until the mean relative
+ * standard deviation over pixels with D >= threshold_frac * max(D) is <= target, or
+ * max_histories have been run.  Reports histories run and the last sigma-bar. */
+epidmc_status epidmc_run_until(epidmc_ctx *c, double target_rel_unc, double threshold_frac,
+                               uint64_t first_history, uint64_t step_histories, uint64_t max_histories,
+                               void *stream, uint64_t *histories_done, double *sigma_bar);
+/* Mean energy per history (MeV) and the variance of that mean (MeV^2), [npx_v][npx_u]
+ * FP64, written to caller device buffers on `stream` (asynchronous). */
+epidmc_status epidmc_read_image(epidmc_ctx *c, double *dev_mean, double *dev_var, void *stream);
+/* Mean relative standard deviation over pixels with D >= threshold_frac * max(D). */
+epidmc_status epidmc_sigma_bar(epidmc_ctx *c, double threshold_frac, void *stream, double *out);
+epidmc_status epidmc_reset_tally(epidmc_ctx *c, void *stream);
+/* Work and diagnostic counters accumulated since the last reset (synchronises). */
+epidmc_status epidmc_get_counters(epidmc_ctx *c, epidmc_counters *out);
+
+/* ---- diagnostics of the device building blocks (test entry points) ----------- */
+/* Philox4x32-10 on the device: out[4*i..4*i+3] = philox(ctr[4*i..], key).  Device pointers. */
+epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *dev_ctr, uint32_t *dev_out, uint64_t n,
+                                  void *stream);
+/* Device samplers: kind 0 Klein-Nishina eps = E'/E at energy p0; kind 1 Moller energy
+ * transfer at kinetic energy p0; kind 2 bremsstrahlung photon energy at p0; kind 3
+ * multiple-scattering polar angle for kinetic energy p0 over p1 g/cm^2 of material p2;
+ * kind 4 the source: 8 floats (x y z u v w E type) per history starting at history
+ * p0.  n samples into dev_out. */
+epidmc_status epidmc_debug_sample(epidmc_ctx *c, int kind, double p0, double p1, double p2, float *dev_out,
+                                  uint64_t n, void *stream);
+/* The device cross-section tables evaluated at energies: kind 0 photon mu/rho of
+ * material slot `index` (phantom slots 0..3, EPID layers 4..), kind 1 electron range,
+ * kind 2 electron hard cross section (phantom slots 0..3, EPID layers 4..). */
+epidmc_status epidmc_debug_table(epidmc_ctx *c, int kind, int index, const float *dev_E, float *dev_out,
+                                 uint64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -35,6 +35,8 @@
 #define WCUT     0.200         /* Moller hard-collision threshold (MeV) */
 #define KCUT     0.010         /* bremsstrahlung hard-photon threshold (MeV) */
 #define NUDGE    1.0e-5        /* cm pushed past a geometric boundary by a boundary-limited step */
+#define SKIN     0.05          /* a boundary-limited step is at least this fraction of the cell's
+                                  smallest dimension (no runs of vanishing steps along a face) */
 #define DE_FRAC  0.9           /* a step may take the energy down to DE_FRAC * T0 at most */
 #define MAX_E_STEPS 1000000
 
@@ -688,7 +690,7 @@ static void transport_photon(ctx_t *c, part_t ph)
 /* distance from p along d to the boundary of the current cell (voxel, or layer slab within
  * the EPID lateral extent) */
 static double cell_distance(const geo_t *g, int region, const double p[3], const double d[3], int *layer_out,
-                            int *m_out, double *rho_out)
+                            int *m_out, double *rho_out, double *smin)
 {
     const orc_config *cf = g->c;
     double lo[3], hi[3];
@@ -696,11 +698,13 @@ static double cell_distance(const geo_t *g, int region, const double p[3], const
         int idx[3]; voxel_of(g, p, idx);
         long v = ((long)idx[2] * cf->ny + idx[1]) * cf->nx + idx[0];
         *m_out = cf->vox_mat[v]; *rho_out = cf->vox_rho[v]; *layer_out = -1;
+        *smin = SKIN * fmin(cf->spacing[0], fmin(cf->spacing[1], cf->spacing[2]));
         for (int a = 0; a < 3; ++a) { lo[a] = g->bmin[a] + idx[a] * cf->spacing[a]; hi[a] = lo[a] + cf->spacing[a]; }
     } else {
         int l = epid_layer_of(g, p);
         if (l < 0) l = (p[2] < g->zl[0]) ? 0 : cf->n_layers - 1;   /* on the entry plane */
         *layer_out = l; *m_out = cf->layer_mat[l]; *rho_out = cf->layer_rho[l];
+        *smin = SKIN * cf->layer_t[l];
         lo[0] = -g->hx; hi[0] = g->hx; lo[1] = -g->hy; hi[1] = g->hy; lo[2] = g->zl[l]; hi[2] = g->zl[l + 1];
     }
     double t = INFINITY;
@@ -718,8 +722,9 @@ static void transport_electron(ctx_t *c, part_t e)
     double T = e.E;
     for (long step = 0;; ++step) {
         if (step > MAX_E_STEPS) { c->err = ORC_E_LOOP; return; }
-        int layer, m; double rho;
-        double sg = cell_distance(g, e.region, e.p, e.d, &layer, &m, &rho) + NUDGE;
+        int layer, m; double rho, smin;
+        const double dist = cell_distance(g, e.region, e.p, e.d, &layer, &m, &rho, &smin);
+        double sg = fmax(dist + NUDGE, smin);
         const orc_material *mat = &cf->mat[m];
         c->cnt->e_steps++;
         if (rho <= 0) {

@@ -1,0 +1,309 @@
+// device.hpp -- gfx950 building blocks of the transport kernels: the counter-based RNG,
+// structure-of-arrays particle queues with wave-aggregated claims and appends, LDS table
+// lookups, region geometry, deposits and the tally.
+#pragma once
+#include "engine.hpp"
+
+namespace epidmc {
+
+// ---------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).  One call yields four 32-bit
+// words.  A particle's stream is keyed by the run seed; its counter is (draw, particle
+// id lo, particle id hi, history), so a trajectory never depends on the thread or queue
+// slot that carries it.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// open-interval uniform from the top 24 bits: (floor(x / 2^8) + 1/2) 2^-24, never 0 or 1
+__device__ __forceinline__ float u01(uint32_t x) { return ((float)(x >> 8) + 0.5f) * 5.9604644775390625e-8f; }
+
+struct Part {
+    float x, y, z, u, v, w, E;
+    uint32_t hist, plo, phi, draw, flags;
+};
+
+__device__ __forceinline__ float4 rnd4(Part &p, const Params &P)
+{
+    const uint4 r = philox10(p.draw++, p.plo, p.phi, p.hist, P.key0, P.key1);
+    return make_float4(u01(r.x), u01(r.y), u01(r.z), u01(r.w));
+}
+
+// a secondary's stream: 64 bits of the parent's stream become its particle id
+__device__ __forceinline__ void make_child(Part &parent, Part &c, const Params &P, uint32_t type)
+{
+    const uint4 r = philox10(parent.draw++, parent.plo, parent.phi, parent.hist, P.key0, P.key1);
+    c.hist = parent.hist;
+    c.plo = r.x;
+    c.phi = r.y;
+    c.draw = 0;
+    c.flags = (parent.flags & ~(F_TYPE | F_UNSCAT | F_LAYER_MASK)) | type;
+}
+
+// ---------------------------------------------------------------------------------
+// queues
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ Part qload(const Queue &q, uint32_t i)
+{
+    Part p;
+    p.x = q.x[i]; p.y = q.y[i]; p.z = q.z[i];
+    p.u = q.u[i]; p.v = q.v[i]; p.w = q.w[i];
+    p.E = q.E[i];
+    p.hist = q.hist[i]; p.plo = q.plo[i]; p.phi = q.phi[i]; p.draw = q.draw[i]; p.flags = q.flags[i];
+    return p;
+}
+
+__device__ __forceinline__ void qstore(const Queue &q, uint32_t i, const Part &p)
+{
+    q.x[i] = p.x; q.y[i] = p.y; q.z[i] = p.z;
+    q.u[i] = p.u; q.v[i] = p.v; q.w[i] = p.w;
+    q.E[i] = p.E;
+    q.hist[i] = p.hist; q.plo[i] = p.plo; q.phi[i] = p.phi; q.draw[i] = p.draw; q.flags[i] = p.flags;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Append to the next-iteration queue of `kind`: the lanes currently executing that have
+// `pred` set take consecutive slots with a single atomic per wave.  Valid in divergent
+// code: the ballot only sees the executing lanes and the leader is one of them.
+__device__ __forceinline__ void qappend(const Params &P, int kind, bool pred, const Part &p)
+{
+    const unsigned long long m = __ballot(pred);
+    if (m == 0) return;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if ((int)lane_id() == leader)
+        base = atomicAdd(&P.cnt_out[kind], (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) {
+        const uint32_t i = base + (uint32_t)__popcll(m & __lanemask_lt());
+        if (i < P.cap[kind]) qstore(P.out[kind], i, p);
+        else atomicOr(P.err, ERR_QUEUE);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// LDS staging of appends: device-scope atomics on one queue counter are the scarce
+// resource (they serialise beyond the XCD caches), so a kernel whose lanes append often
+// stages particles in a per-wave LDS buffer and appends them to the global queue in bulk.
+// ---------------------------------------------------------------------------------
+// A wave's staging buffers: 12 x SBUF words (structure of arrays) followed by the fill
+// count, in LDS, for electrons entering the phantom queue (e) and photons entering the
+// EPID queue (g); null when the kernel appends directly.
+struct Stages {
+    uint32_t *e, *g;
+};
+
+__device__ __forceinline__ void stage_put(uint32_t *w, uint32_t i, const Part &p)
+{
+    w[0 * SBUF + i] = __float_as_uint(p.x); w[1 * SBUF + i] = __float_as_uint(p.y);
+    w[2 * SBUF + i] = __float_as_uint(p.z); w[3 * SBUF + i] = __float_as_uint(p.u);
+    w[4 * SBUF + i] = __float_as_uint(p.v); w[5 * SBUF + i] = __float_as_uint(p.w);
+    w[6 * SBUF + i] = __float_as_uint(p.E); w[7 * SBUF + i] = p.hist;
+    w[8 * SBUF + i] = p.plo; w[9 * SBUF + i] = p.phi; w[10 * SBUF + i] = p.draw; w[11 * SBUF + i] = p.flags;
+}
+
+__device__ __forceinline__ Part stage_get(const uint32_t *w, uint32_t i)
+{
+    Part p;
+    p.x = __uint_as_float(w[0 * SBUF + i]); p.y = __uint_as_float(w[1 * SBUF + i]);
+    p.z = __uint_as_float(w[2 * SBUF + i]); p.u = __uint_as_float(w[3 * SBUF + i]);
+    p.v = __uint_as_float(w[4 * SBUF + i]); p.w = __uint_as_float(w[5 * SBUF + i]);
+    p.E = __uint_as_float(w[6 * SBUF + i]); p.hist = w[7 * SBUF + i];
+    p.plo = w[8 * SBUF + i]; p.phi = w[9 * SBUF + i]; p.draw = w[10 * SBUF + i]; p.flags = w[11 * SBUF + i];
+    return p;
+}
+
+// append one particle per lane with `pred`, through the wave's staging buffer when the kind
+// has one; valid in divergent code (the slot comes from an LDS atomic); a full buffer spills
+// straight to the queue
+__device__ __forceinline__ void append(const Params &P, Stages S, int kind, bool pred, const Part &p)
+{
+    uint32_t *w = kind == QEP ? S.e : kind == QGE ? S.g : nullptr;
+    if (!w) {
+        qappend(P, kind, pred, p);
+        return;
+    }
+    if (!pred) return;
+    const uint32_t i = atomicAdd(w + 12 * SBUF, 1u);
+    if (i < SBUF) {
+        stage_put(w, i, p);
+    } else {
+        const uint32_t g = atomicAdd(&P.cnt_out[kind], 1u);
+        if (g < P.cap[kind]) qstore(P.out[kind], g, p);
+        else atomicOr(P.err, ERR_QUEUE);
+    }
+}
+
+// move a wave's staged particles to the global queue `kind` when at least `minfill` are
+// waiting; call with the wave converged
+__device__ __forceinline__ void stage_flush(const Params &P, uint32_t *w, int kind, uint32_t minfill)
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t n = min(w[12 * SBUF], (uint32_t)SBUF);
+    if (n == 0 || n < minfill) return;
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(&P.cnt_out[kind], n);
+    base = __shfl(base, 0);
+    for (uint32_t i = lane_id(); i < n; i += 64) {
+        const Part q = stage_get(w, i);
+        if (base + i < P.cap[kind]) qstore(P.out[kind], base + i, q);
+        else atomicOr(P.err, ERR_QUEUE);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane_id() == 0) w[12 * SBUF] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Wave-uniform window of queue items claimed WIN at a time.
+struct Win {
+    uint32_t b, e;
+    int done;
+};
+
+// Give every idle lane of a converged wave the next unclaimed particle of queue `kind`.
+__device__ __forceinline__ void refill(const Params &P, int kind, uint32_t n, Win &win, bool &active, Part &p)
+{
+    const Queue &q = P.in[kind];
+    unsigned long long need = __ballot(!active);
+    while (need) {
+        if (win.b >= win.e) {
+            if (win.done) break;
+            uint32_t b = 0;
+            if (lane_id() == 0) b = atomicAdd(&P.heads[kind], (uint32_t)WIN);
+            b = __shfl(b, 0);
+            if (b >= n) { win.done = 1; break; }
+            win.b = b;
+            win.e = min(b + (uint32_t)WIN, n);
+        }
+        const uint32_t avail = win.e - win.b;
+        const uint32_t rank = (uint32_t)__popcll(need & __lanemask_lt());
+        if (!active && rank < avail) {
+            p = qload(q, win.b + rank);
+            active = true;
+        }
+        win.b += min((uint32_t)__popcll(need), avail);
+        need = __ballot(!active);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// tables: node i at ln E0 + i / idl; linear interpolation in ln E
+// ---------------------------------------------------------------------------------
+struct Node {
+    int i;
+    float f;
+};
+__device__ __forceinline__ Node node_of(float lnE, float lnE0, float idl, int nb)
+{
+    float t = (lnE - lnE0) * idl;
+    t = fminf(fmaxf(t, 0.0f), (float)(nb - 1) - 1e-3f);
+    Node n;
+    n.i = (int)t;
+    n.f = t - (float)n.i;
+    return n;
+}
+__device__ __forceinline__ float lerp_tab(const float *t, Node n) { return fmaf(n.f, t[n.i + 1] - t[n.i], t[n.i]); }
+
+// ---------------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ bool in_phantom(const Params &P, float x, float y, float z)
+{
+    return x >= 0.0f && x < P.Lx && y >= 0.0f && y < P.Ly && z >= 0.0f && z < P.Lz;
+}
+
+__device__ __forceinline__ int epid_layer(const Params &P, float x, float y, float z)
+{
+    if (!(x >= -P.hx && x < P.hx && y >= -P.hy && y < P.hy)) return -1;
+    if (!(z >= 0.0f && z < P.zback)) return -1;
+    int l = 0;
+#pragma unroll
+    for (int k = 1; k < MAX_LAYERS; ++k)
+        if (k < P.nl && z >= P.zl[k]) l = k;
+    return l;
+}
+
+// rotate the unit vector (u,v,w) by polar angle (ct, st) and azimuth (cp, sp)
+__device__ __forceinline__ void rotate(float &u, float &v, float &w, float ct, float st, float cp, float sp)
+{
+    const float s2 = fmaf(-w, w, 1.0f);
+    float nu, nv, nw;
+    if (s2 > 1e-10f) {
+        const float s = sqrtf(s2), is = 1.0f / s;
+        nu = u * ct + st * (u * w * cp - v * sp) * is;
+        nv = v * ct + st * (v * w * cp + u * sp) * is;
+        nw = w * ct - st * cp * s;
+    } else {
+        nu = st * cp;
+        nv = st * sp;
+        nw = (w >= 0.0f ? ct : -ct);
+    }
+    const float r = rsqrtf(nu * nu + nv * nv + nw * nw);
+    u = nu * r; v = nv * r; w = nw * r;
+}
+
+// ---------------------------------------------------------------------------------
+// deposits
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ void ledger(const Params &P, uint32_t hist, double e)
+{
+    if (P.diag) atomicAdd(&P.led[hist - (uint32_t)P.h0], e);
+}
+
+__device__ __forceinline__ void tally(const Params &P, uint32_t flags, float x, float y, float e)
+{
+    const float fu = floorf((x + P.hx) * P.ipu), fv = floorf((y + P.hy) * P.ipv);
+    if (!(fu >= 0.0f && fu < (float)P.npx_u && fv >= 0.0f && fv < (float)P.npx_v) || !(e > 0.0f)) return;
+    const uint32_t pix = (uint32_t)fv * (uint32_t)P.npx_u + (uint32_t)fu;
+    const uint32_t slot = flags >> F_SLOT_SHIFT;
+    if (P.tally_mode == 0) {
+        unsafeAtomicAdd((double *)P.img + (size_t)slot * P.npix + pix, (double)e);
+    } else if (P.tally_mode == 1) {
+        const long long q = __double2ll_rn((double)e * 4294967296.0);
+        atomicAdd((unsigned long long *)P.img + (size_t)slot * P.npix + pix, (unsigned long long)q);
+    } else {
+        const unsigned long long m = __ballot(1);
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if ((int)lane_id() == leader) base = atomicAdd(&P.cnt[3 * NQ], (uint32_t)__popcll(m));
+        base = __shfl(base, leader);
+        const uint32_t i = base + (uint32_t)__popcll(m & __lanemask_lt());
+        if (i < P.rec_cap) {
+            P.rec_pix[i] = slot * P.npix + pix;
+            P.rec_e[i] = e;
+        } else {
+            atomicOr(P.err, ERR_QUEUE);
+        }
+    }
+}
+
+// point deposit in the EPID located by position (tallied in the scoring layer)
+__device__ __forceinline__ void deposit_epid_point(const Params &P, const Part &p, float e, unsigned &ntally)
+{
+    if (epid_layer(P, p.x, p.y, p.z) == P.scoring) {
+        tally(P, p.flags, p.x, p.y, e);
+        ++ntally;
+    }
+}
+
+}  // namespace epidmc

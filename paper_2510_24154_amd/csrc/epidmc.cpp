@@ -1,0 +1,1036 @@
+// epidmc.cpp -- C ABI, model validation, workspace layout and the queue-pass orchestrator.
+#include "../../include/epidmc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "tables.hpp"
+
+namespace epidmc {
+hipError_t launch_source(const Params &P, hipStream_t s);
+hipError_t launch_transport(int kind, const Params &P, unsigned blocks, hipStream_t s);
+size_t lds_bytes(int kind, const Params &P);
+hipError_t set_lds_limits();
+hipError_t launch_fold(const Params &P, const int *slots, const double *nb, int n, hipStream_t s);
+hipError_t launch_kahan_reduce(const Params &P, uint32_t nrec, uint32_t nimg, uint32_t *count, uint32_t *cursor,
+                               uint32_t *bsum, float *sorted, hipStream_t s);
+hipError_t launch_image(const Params &P, double n, double nb, double *mean, double *var, hipStream_t s);
+hipError_t launch_sigma_bar(const Params &P, double n, double nb, double thr, double *out, hipStream_t s);
+hipError_t launch_diag_check(const Params &P, uint32_t nh, unsigned long long *maxbits, double *sums, hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_dbg_philox(const Params &P, const uint32_t *ctr, uint32_t *out, unsigned long long n, hipStream_t s);
+hipError_t launch_dbg_sample(const Params &P, int kind, float p0, float p1, float p2, float *out,
+                             unsigned long long n, hipStream_t s);
+hipError_t launch_dbg_table(const Params &P, int kind, int index, const float *E, float *out, unsigned long long n,
+                            hipStream_t s);
+}  // namespace epidmc
+
+using namespace epidmc;
+
+namespace {
+
+struct Region {
+    size_t off, bytes;
+};
+
+struct Layout {
+    Region vox, ph_tab, ph_maj, el_tab, sp_lo, sp_hi, sp_prob, sp_alias, ap_a, ap_b, ap_prob, ap_alias, seg_end,
+        phsp, ctl, queues, img, sum, sum2, led, ein, rec_pix, rec_e, k_count, k_cursor, k_bsum, k_sorted;
+    size_t total;
+    uint32_t cap[NQ];
+    uint32_t rec_cap;
+    int ring;
+    uint64_t chunk;
+};
+
+constexpr size_t CTL_CNT = 0;                 // 16 u32: [2][NQ] counts, [NQ] heads, record count
+constexpr size_t CTL_ERR = 64;                // u32
+constexpr size_t CTL_STATS = 128;             // S_NSTAT u64
+constexpr size_t CTL_DIAG = CTL_STATS + 8 * 32;   // max-residual bits, e_in, e_ledger
+constexpr size_t CTL_SIGMA = CTL_DIAG + 64;   // double
+constexpr size_t CTL_BYTES = 1024;
+
+}  // namespace
+
+struct epidmc_ctx {
+    int device = 0;
+    uint64_t seed = 0;
+    std::string err;
+    int n_cu = 256;
+    // model
+    std::vector<HostMaterial> mats;
+    int coupled = 1;
+    uint32_t mask = 7u;
+    float pcut = 0.010f, ecut = 0.200f;
+    int nx = 0, ny = 0, nz = 0;
+    float spacing[3] = {0, 0, 0}, origin[3] = {0, 0, 0};
+    std::vector<uint8_t> vmat;     // global material index per voxel
+    std::vector<float> vrho;
+    std::vector<epidmc_layer> layers;
+    int scoring = 0;
+    float front_z = 0;
+    int npx_u = 0, npx_v = 0;
+    float pitch_u = 0, pitch_v = 0;
+    std::vector<float> edges, weights;
+    epidmc_beam beam{};
+    bool have_spectrum = false;
+    std::vector<float> phsp;
+    uint64_t n_phsp = 0;
+    int n_seg = 0, n_pairs = 0;
+    float leaf_w = 0, y0 = 0;
+    std::vector<float> ap_a, ap_b;
+    std::vector<uint64_t> seg_hist;
+    int tally_mode = 0, batches = 64;
+    uint64_t max_chunk = 1ull << 21;
+    int diag = 0;
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    Layout lay{};
+    Params P{};
+    Queue qs[2][NQ];                // the two queue buffer sets
+    int slot_of_mat[EPIDMC_MAX_MATERIALS];
+    uint32_t *host = nullptr;       // pinned readback area
+    int occ[NQ] = {1, 1, 1, 1};
+    // profiling
+    int prof = 0;
+    hipEvent_t ev[2][NQ] = {};
+    double kernel_ms[NQ] = {0, 0, 0, 0};
+    uint64_t kernel_launches[NQ] = {0, 0, 0, 0};
+    // accumulated
+    double n_total = 0, b_total = 0;
+    uint64_t launches = 0, queue_peak = 0;
+};
+
+static epidmc_status fail(epidmc_ctx *c, epidmc_status s, const std::string &m)
+{
+    if (c) c->err = m;
+    return s;
+}
+#define REQUIRE(cond, code, msg) \
+    do { if (!(cond)) return fail(c, code, msg); } while (0)
+#define HIPCHK(x)                                                                                          \
+    do {                                                                                                   \
+        hipError_t e_ = (x);                                                                               \
+        if (e_ != hipSuccess) return fail(c, EPIDMC_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static bool finite3(const float v[3]) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+static void unbind(epidmc_ctx *c) { c->bound = false; }
+
+extern "C" {
+
+epidmc_status epidmc_create(epidmc_ctx **out, int device, uint64_t seed)
+{
+    if (!out) return EPIDMC_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EPIDMC_E_DEVICE;
+    epidmc_ctx *c = new epidmc_ctx();
+    c->device = device;
+    c->seed = seed;
+    if (hipSetDevice(device) != hipSuccess) { delete c; return EPIDMC_E_DEVICE; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) { delete c; return EPIDMC_E_DEVICE; }
+    // raise the dynamic LDS cap of the transport kernels where the device allows it; the
+    // default cap already covers up to five EPID layers
+    (void)set_lds_limits();
+    (void)hipGetLastError();
+    *out = c;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_destroy(epidmc_ctx *c)
+{
+    if (!c) return EPIDMC_E_ARG;
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < NQ; ++k)
+            if (c->ev[b][k]) (void)hipEventDestroy(c->ev[b][k]);
+    if (c->host) (void)hipHostFree(c->host);
+    delete c;
+    return EPIDMC_OK;
+}
+
+const char *epidmc_last_error(const epidmc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+epidmc_status epidmc_set_materials(epidmc_ctx *c, const epidmc_material *m, int n)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(m && n >= 1 && n <= EPIDMC_MAX_MATERIALS, EPIDMC_E_ARG, "1..16 materials required");
+    std::vector<HostMaterial> v(n);
+    for (int i = 0; i < n; ++i) {
+        REQUIRE(m[i].n_elem >= 1 && m[i].n_elem <= EPIDMC_MAX_ELEM, EPIDMC_E_ARG, "material element count");
+        REQUIRE(std::isfinite(m[i].I_eV) && m[i].I_eV > 0, EPIDMC_E_ARG, "material I-value must be > 0");
+        double ws = 0;
+        v[i].n = m[i].n_elem;
+        for (int k = 0; k < m[i].n_elem; ++k) {
+            REQUIRE(m[i].Z[k] >= 1 && m[i].Z[k] <= 100, EPIDMC_E_RANGE, "element Z out of range");
+            REQUIRE(std::isfinite(m[i].A[k]) && m[i].A[k] > 0, EPIDMC_E_ARG, "element A must be > 0");
+            REQUIRE(std::isfinite(m[i].w[k]) && m[i].w[k] >= 0, EPIDMC_E_ARG, "mass fraction must be >= 0");
+            v[i].Z[k] = m[i].Z[k];
+            v[i].A[k] = m[i].A[k];
+            v[i].w[k] = m[i].w[k];
+            ws += m[i].w[k];
+        }
+        REQUIRE(ws > 0, EPIDMC_E_ARG, "mass fractions sum to zero");
+        v[i].I_eV = m[i].I_eV;
+    }
+    c->mats = v;
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_physics(epidmc_ctx *c, epidmc_phys_mode mode, uint32_t mask, float pcut, float ecut)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(mode == EPIDMC_PHYS_KERMA || mode == EPIDMC_PHYS_COUPLED, EPIDMC_E_ARG, "unknown physics mode");
+    REQUIRE((mask & 7u) != 0 && mask < 32u, EPIDMC_E_ARG, "process mask needs a photon process, bits 0..4 only");
+    REQUIRE(std::isfinite(pcut) && pcut >= 1e-3f && pcut < 1.0f, EPIDMC_E_RANGE, "photon cut-off in [1 keV, 1 MeV)");
+    REQUIRE(std::isfinite(ecut) && ecut >= 0.05f && ecut < 2.0f, EPIDMC_E_RANGE, "electron cut-off in [50 keV, 2 MeV)");
+    REQUIRE(ecut >= (float)WCUT - 1e-6f || mode == EPIDMC_PHYS_KERMA, EPIDMC_E_RANGE,
+            "coupled transport needs an electron cut-off >= the 200 keV Moller threshold");
+    c->coupled = mode == EPIDMC_PHYS_COUPLED;
+    c->mask = mask;
+    c->pcut = pcut;
+    c->ecut = ecut;
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+static epidmc_status check_grid(epidmc_ctx *c, int nx, int ny, int nz, const float sp[3], const float org[3])
+{
+    REQUIRE(nx > 0 && ny > 0 && nz > 0, EPIDMC_E_SHAPE, "phantom dimensions must be > 0");
+    REQUIRE((uint64_t)nx * ny * nz <= (1ull << 31), EPIDMC_E_RANGE, "phantom larger than 2^31 voxels");
+    REQUIRE(sp && org && finite3(sp) && finite3(org), EPIDMC_E_ARG, "spacing/origin must be finite");
+    REQUIRE(sp[0] > 0 && sp[1] > 0 && sp[2] > 0, EPIDMC_E_ARG, "spacing must be > 0");
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_phantom_direct(epidmc_ctx *c, const uint8_t *mat, const float *rho, int nx, int ny, int nz,
+                                        const float sp[3], const float org[3])
+{
+    if (!c) return EPIDMC_E_ARG;
+    epidmc_status s = check_grid(c, nx, ny, nz, sp, org);
+    if (s != EPIDMC_OK) return s;
+    REQUIRE(mat && rho, EPIDMC_E_ARG, "null phantom arrays");
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t i = 0; i < n; ++i) {
+        REQUIRE(std::isfinite(rho[i]) && rho[i] >= 0.0f && rho[i] < 1e4f, EPIDMC_E_ARG, "voxel density must be finite and >= 0");
+        REQUIRE(mat[i] < c->mats.size(), EPIDMC_E_RANGE, "voxel material index not in the material table");
+    }
+    c->vmat.assign(mat, mat + n);
+    c->vrho.assign(rho, rho + n);
+    c->nx = nx; c->ny = ny; c->nz = nz;
+    std::memcpy(c->spacing, sp, sizeof c->spacing);
+    std::memcpy(c->origin, org, sizeof c->origin);
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_phantom_hu(epidmc_ctx *c, const int16_t *hu, int nx, int ny, int nz, const float sp[3],
+                                    const float org[3], const epidmc_hu_curve *cv)
+{
+    if (!c) return EPIDMC_E_ARG;
+    epidmc_status s = check_grid(c, nx, ny, nz, sp, org);
+    if (s != EPIDMC_OK) return s;
+    REQUIRE(hu && cv && cv->hu && cv->rho && cv->hu_upper && cv->material, EPIDMC_E_ARG, "null HU inputs");
+    REQUIRE(cv->n_points >= 1 && cv->n_ranges >= 1, EPIDMC_E_ARG, "HU curve needs points and ranges");
+    for (int k = 0; k < cv->n_points; ++k) {
+        REQUIRE(std::isfinite(cv->hu[k]) && std::isfinite(cv->rho[k]) && cv->rho[k] >= 0, EPIDMC_E_ARG, "HU curve values");
+        if (k) REQUIRE(cv->hu[k] > cv->hu[k - 1], EPIDMC_E_ARG, "HU curve points must ascend");
+    }
+    for (int r = 0; r < cv->n_ranges; ++r)
+        REQUIRE(cv->material[r] >= 0 && cv->material[r] < (int)c->mats.size(), EPIDMC_E_RANGE,
+                "HU range material not in the material table");
+    const size_t n = (size_t)nx * ny * nz;
+    std::vector<uint8_t> m(n);
+    std::vector<float> rho(n);
+    for (size_t i = 0; i < n; ++i) {
+        const double x = hu[i];
+        double r;
+        if (x <= cv->hu[0]) r = cv->rho[0];
+        else if (x >= cv->hu[cv->n_points - 1]) r = cv->rho[cv->n_points - 1];
+        else {
+            int k = 0;
+            while (!(x < cv->hu[k + 1])) ++k;
+            r = cv->rho[k] + (cv->rho[k + 1] - cv->rho[k]) * (x - cv->hu[k]) / (cv->hu[k + 1] - cv->hu[k]);
+        }
+        int rr = cv->n_ranges - 1;
+        for (int k = 0; k < cv->n_ranges - 1; ++k)
+            if (x < cv->hu_upper[k]) { rr = k; break; }
+        m[i] = (uint8_t)cv->material[rr];
+        rho[i] = (float)r;
+    }
+    c->vmat.swap(m);
+    c->vrho.swap(rho);
+    c->nx = nx; c->ny = ny; c->nz = nz;
+    std::memcpy(c->spacing, sp, sizeof c->spacing);
+    std::memcpy(c->origin, org, sizeof c->origin);
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_epid(epidmc_ctx *c, const epidmc_layer *layers, int nl, int scoring, float front_z, int npx_u,
+                              int npx_v, float pitch_u, float pitch_v)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(layers && nl >= 1 && nl <= EPIDMC_MAX_LAYERS, EPIDMC_E_ARG, "1..6 EPID layers");
+    REQUIRE(scoring >= 0 && scoring < nl, EPIDMC_E_RANGE, "scoring layer index");
+    REQUIRE(std::isfinite(front_z), EPIDMC_E_ARG, "front_z must be finite");
+    REQUIRE(npx_u > 0 && npx_v > 0 && (uint64_t)npx_u * npx_v <= (1ull << 26), EPIDMC_E_SHAPE, "image size");
+    REQUIRE(std::isfinite(pitch_u) && std::isfinite(pitch_v) && pitch_u > 0 && pitch_v > 0, EPIDMC_E_ARG, "pitch must be > 0");
+    for (int l = 0; l < nl; ++l) {
+        REQUIRE(layers[l].material >= 0 && layers[l].material < (int)c->mats.size(), EPIDMC_E_RANGE, "layer material");
+        REQUIRE(std::isfinite(layers[l].thickness) && layers[l].thickness > 0, EPIDMC_E_ARG, "layer thickness > 0");
+        REQUIRE(std::isfinite(layers[l].density) && layers[l].density >= 0, EPIDMC_E_ARG, "layer density >= 0");
+    }
+    c->layers.assign(layers, layers + nl);
+    c->scoring = scoring;
+    c->front_z = front_z;
+    c->npx_u = npx_u; c->npx_v = npx_v;
+    c->pitch_u = pitch_u; c->pitch_v = pitch_v;
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_source_spectrum(epidmc_ctx *c, const float *edges, const float *w, int nbins, const epidmc_beam *beam)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(edges && w && beam && nbins >= 1 && nbins <= 65536, EPIDMC_E_ARG, "spectrum arrays");
+    REQUIRE(beam->kind == 0 || beam->kind == 1, EPIDMC_E_ARG, "beam kind 0 (parallel) or 1 (point)");
+    REQUIRE(finite3(beam->src) && std::isfinite(beam->iso_z), EPIDMC_E_ARG, "beam geometry must be finite");
+    REQUIRE(beam->kind == 0 || beam->iso_z != beam->src[2], EPIDMC_E_ARG, "point source on its aperture plane");
+    double tot = 0;
+    for (int i = 0; i < nbins; ++i) {
+        REQUIRE(std::isfinite(w[i]) && w[i] >= 0, EPIDMC_E_ARG, "spectrum weights must be >= 0");
+        tot += w[i];
+    }
+    REQUIRE(tot > 0, EPIDMC_E_ARG, "spectrum weights sum to zero");
+    for (int i = 0; i <= nbins; ++i) {
+        REQUIRE(std::isfinite(edges[i]), EPIDMC_E_ARG, "bin edges must be finite");
+        if (i) REQUIRE(edges[i] >= edges[i - 1], EPIDMC_E_ARG, "bin edges must not decrease");
+    }
+    REQUIRE(edges[nbins] <= 50.0f, EPIDMC_E_RANGE, "energies above 50 MeV are not supported");
+    c->edges.assign(edges, edges + nbins + 1);
+    c->weights.assign(w, w + nbins);
+    c->beam = *beam;
+    c->have_spectrum = true;
+    c->phsp.clear();
+    c->n_phsp = 0;
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_source_phsp(epidmc_ctx *c, const epidmc_particle *p, uint64_t n)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(p && n >= 1 && n <= (1ull << 28), EPIDMC_E_ARG, "phase-space list");
+    std::vector<float> v(8 * n);
+    for (uint64_t i = 0; i < n; ++i) {
+        const epidmc_particle &q = p[i];
+        REQUIRE(q.type == 0 || q.type == 1, EPIDMC_E_ARG, "phase-space particles are photons (0) or electrons (1)");
+        REQUIRE(std::isfinite(q.x) && std::isfinite(q.y) && std::isfinite(q.z) && std::isfinite(q.E), EPIDMC_E_ARG,
+                "phase-space values must be finite");
+        REQUIRE(q.E > 0 && q.E <= 50.0f, EPIDMC_E_RANGE, "phase-space energy in (0, 50] MeV");
+        const double nn = std::sqrt((double)q.u * q.u + (double)q.v * q.v + (double)q.w * q.w);
+        REQUIRE(std::fabs(nn - 1.0) < 1e-3, EPIDMC_E_ARG, "phase-space directions must be unit vectors");
+        const float f[8] = {q.x, q.y, q.z, (float)(q.u / nn), (float)(q.v / nn), (float)(q.w / nn), q.E, (float)q.type};
+        std::memcpy(&v[8 * i], f, sizeof f);
+    }
+    c->phsp.swap(v);
+    c->n_phsp = n;
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_segments(epidmc_ctx *c, int n_seg, int n_pairs, float leaf_w, float y0, const float *a,
+                                  const float *b, const uint64_t *n_hist)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(n_seg >= 1 && n_seg <= EPIDMC_MAX_SEGMENTS && n_pairs >= 1 && n_pairs <= 1024 && a && b, EPIDMC_E_ARG,
+            "segments: 1..256 segments, 1..1024 leaf pairs");
+    REQUIRE(std::isfinite(leaf_w) && leaf_w > 0 && std::isfinite(y0), EPIDMC_E_ARG, "leaf width > 0");
+    REQUIRE(n_seg == 1 || n_hist, EPIDMC_E_ARG, "several segments need history counts");
+    for (int s = 0; s < n_seg; ++s) {
+        double open = 0;
+        for (int k = 0; k < n_pairs; ++k) {
+            const float lo = a[s * n_pairs + k], hi = b[s * n_pairs + k];
+            REQUIRE(std::isfinite(lo) && std::isfinite(hi) && lo <= hi, EPIDMC_E_ARG, "leaf positions need a <= b");
+            open += hi - lo;
+        }
+        REQUIRE(open > 0 || (n_seg > 1 && n_hist[s] == 0), EPIDMC_E_ARG, "a segment with histories has no open area");
+    }
+    uint64_t tot = 0;
+    if (n_seg > 1)
+        for (int s = 0; s < n_seg; ++s) tot += n_hist[s];
+    REQUIRE(tot <= (1ull << 32), EPIDMC_E_RANGE, "history ids must stay below 2^32");
+    c->n_seg = n_seg;
+    c->n_pairs = n_pairs;
+    c->leaf_w = leaf_w;
+    c->y0 = y0;
+    c->ap_a.assign(a, a + (size_t)n_seg * n_pairs);
+    c->ap_b.assign(b, b + (size_t)n_seg * n_pairs);
+    c->seg_hist.assign(n_seg, 0);
+    if (n_seg > 1) std::copy(n_hist, n_hist + n_seg, c->seg_hist.begin());
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_tally(epidmc_ctx *c, epidmc_tally_mode mode, int batches, uint64_t max_chunk)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(mode >= EPIDMC_TALLY_FP64 && mode <= EPIDMC_TALLY_KAHAN32, EPIDMC_E_ARG, "unknown tally mode");
+    REQUIRE(batches >= 2 && batches <= 1 << 20, EPIDMC_E_ARG, "batches per run in [2, 2^20]");
+    REQUIRE(max_chunk >= 1024 && max_chunk <= (1ull << 27), EPIDMC_E_RANGE, "chunk in [1024, 2^27] histories");
+    c->tally_mode = (int)mode;
+    c->batches = batches;
+    c->max_chunk = max_chunk;
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_profiling(epidmc_ctx *c, int enable)
+{
+    if (!c) return EPIDMC_E_ARG;
+    if (enable && !c->ev[0][0]) {
+        HIPCHK(hipSetDevice(c->device));
+        for (int b = 0; b < 2; ++b)
+            for (int k = 0; k < NQ; ++k) HIPCHK(hipEventCreate(&c->ev[b][k]));
+    }
+    c->prof = enable ? 1 : 0;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_diagnostics(epidmc_ctx *c, int enable)
+{
+    if (!c) return EPIDMC_E_ARG;
+    c->diag = enable ? 1 : 0;
+    unbind(c);
+    return EPIDMC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// layout
+// ---------------------------------------------------------------------------------
+static epidmc_status model_ready(epidmc_ctx *c)
+{
+    REQUIRE(!c->mats.empty(), EPIDMC_E_NOT_READY, "materials not set");
+    REQUIRE(c->nx > 0, EPIDMC_E_NOT_READY, "phantom not set");
+    REQUIRE(!c->layers.empty(), EPIDMC_E_NOT_READY, "EPID not set");
+    REQUIRE(c->have_spectrum || c->n_phsp > 0, EPIDMC_E_NOT_READY, "source not set");
+    REQUIRE(c->n_phsp > 0 || c->n_seg > 0, EPIDMC_E_NOT_READY, "aperture segments not set");
+    for (size_t i = 0; i < c->vmat.size(); ++i)
+        REQUIRE(c->vmat[i] < c->mats.size(), EPIDMC_E_RANGE, "voxel material not in the material table");
+    for (auto &l : c->layers) REQUIRE(l.material < (int)c->mats.size(), EPIDMC_E_RANGE, "layer material not in the table");
+    // distinct phantom materials
+    bool seen[EPIDMC_MAX_MATERIALS] = {false};
+    for (uint8_t m : c->vmat) seen[m] = true;
+    int k = 0;
+    for (int m = 0; m < EPIDMC_MAX_MATERIALS; ++m) {
+        c->slot_of_mat[m] = -1;
+        if (seen[m]) c->slot_of_mat[m] = k++;
+    }
+    REQUIRE(k <= MAX_PMAT, EPIDMC_E_RANGE, "at most 4 distinct materials in one phantom");
+    return EPIDMC_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static Layout make_layout(const epidmc_ctx *c)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](Region &r, size_t bytes) { r.off = off; r.bytes = bytes; off = align256(off + bytes); };
+    const size_t nvox = (size_t)c->nx * c->ny * c->nz;
+    const size_t npix = (size_t)c->npx_u * c->npx_v;
+    const uint64_t H = c->max_chunk;
+    L.chunk = H;
+    L.cap[QGP] = (uint32_t)(H + 4096);
+    L.cap[QEP] = (uint32_t)(4 * H + 4096);
+    L.cap[QGE] = (uint32_t)(2 * H + 4096);
+    L.cap[QEE] = (uint32_t)(2 * H + 4096);
+    L.rec_cap = c->tally_mode == 2 ? (uint32_t)(8 * H + 4096) : 0;
+    L.ring = std::min(c->batches, MAX_SLOTS);
+    const int nbins = std::max<int>(1, (int)c->weights.size());
+    const size_t nap = (size_t)std::max(1, c->n_seg) * std::max(1, c->n_pairs);
+    take(L.vox, nvox * 4);
+    take(L.ph_tab, (size_t)(MAX_PMAT + MAX_LAYERS) * 3 * NB_PH * 4);
+    take(L.ph_maj, NB_PH * 4);
+    take(L.el_tab, (size_t)(MAX_PMAT + MAX_LAYERS) * 3 * NB_EL * 4);
+    take(L.sp_lo, nbins * 4);
+    take(L.sp_hi, nbins * 4);
+    take(L.sp_prob, nbins * 4);
+    take(L.sp_alias, nbins * 4);
+    take(L.ap_a, nap * 4);
+    take(L.ap_b, nap * 4);
+    take(L.ap_prob, nap * 4);
+    take(L.ap_alias, nap * 4);
+    take(L.seg_end, (size_t)std::max(1, c->n_seg) * 8);
+    take(L.phsp, std::max<size_t>(1, c->n_phsp) * 32);
+    take(L.ctl, CTL_BYTES);
+    size_t qb = 0;
+    for (int k = 0; k < NQ; ++k) qb += (size_t)L.cap[k] * 48;
+    take(L.queues, 2 * qb);
+    take(L.img, (size_t)L.ring * npix * 8);
+    take(L.sum, npix * 8);
+    take(L.sum2, npix * 8);
+    take(L.led, c->diag ? H * 8 : 8);
+    take(L.ein, c->diag ? H * 8 : 8);
+    const size_t nimg = (size_t)L.ring * npix;
+    take(L.rec_pix, (size_t)L.rec_cap * 4 + 4);
+    take(L.rec_e, (size_t)L.rec_cap * 4 + 4);
+    take(L.k_count, c->tally_mode == 2 ? nimg * 4 : 4);
+    take(L.k_cursor, c->tally_mode == 2 ? nimg * 4 : 4);
+    take(L.k_bsum, c->tally_mode == 2 ? (nimg / 1024 + 2) * 4 : 4);
+    take(L.k_sorted, (size_t)L.rec_cap * 4 + 4);
+    L.total = off;
+    return L;
+}
+
+extern "C" epidmc_status epidmc_workspace_size(epidmc_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return EPIDMC_E_ARG;
+    epidmc_status s = model_ready(c);
+    if (s != EPIDMC_OK) return s;
+    *bytes = make_layout(c).total;
+    return EPIDMC_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// binding: build tables and upload
+// ---------------------------------------------------------------------------------
+extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t bytes, void *stream)
+{
+    if (!c) return EPIDMC_E_ARG;
+    epidmc_status st = model_ready(c);
+    if (st != EPIDMC_OK) return st;
+    REQUIRE(dev && ((uintptr_t)dev % 256) == 0, EPIDMC_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const Layout L = make_layout(c);
+    REQUIRE(bytes >= L.total, EPIDMC_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)dev;
+
+    // energy grids
+    float emax = 0.52f;
+    for (float e : c->edges) emax = std::max(emax, e);
+    for (uint64_t i = 0; i < c->n_phsp; ++i) emax = std::max(emax, c->phsp[8 * i + 6]);
+    const double ehi = 1.02 * emax;
+    const double ph0 = std::log((double)c->pcut), phd = (std::log(ehi) - ph0) / (NB_PH - 1);
+    const double el0 = std::log(0.5 * (double)c->ecut), eld = (std::log(ehi) - el0) / (NB_EL - 1);
+
+    // phantom packing: density bits with the two low bits replaced by the material slot
+    const size_t nvox = c->vmat.size();
+    std::vector<uint32_t> vox(nvox);
+    float rho_max[MAX_PMAT] = {0, 0, 0, 0};
+    int mat_of_slot[MAX_PMAT] = {0, 0, 0, 0};
+    int nslot = 0;
+    for (int m = 0; m < EPIDMC_MAX_MATERIALS; ++m)
+        if (c->slot_of_mat[m] >= 0) { mat_of_slot[c->slot_of_mat[m]] = m; nslot = std::max(nslot, c->slot_of_mat[m] + 1); }
+    for (size_t i = 0; i < nvox; ++i) {
+        uint32_t bits;
+        std::memcpy(&bits, &c->vrho[i], 4);
+        const uint32_t slot = (uint32_t)c->slot_of_mat[c->vmat[i]];
+        vox[i] = (bits & ~3u) | slot;
+        float r;
+        const uint32_t rb = bits & ~3u;
+        std::memcpy(&r, &rb, 4);
+        rho_max[slot] = std::max(rho_max[slot], r);
+    }
+
+    // tables
+    std::vector<float> ph_tab((size_t)(MAX_PMAT + MAX_LAYERS) * 3 * NB_PH, 0.0f);
+    std::vector<float> el_tab((size_t)(MAX_PMAT + MAX_LAYERS) * 3 * NB_EL, 0.0f);
+    std::vector<float> maj(NB_PH, 0.0f);
+    float x0[MAX_PMAT + MAX_LAYERS] = {0};
+    auto build_slot = [&](int slot, int mat) {
+        const MatDerived d = derive(c->mats[mat]);
+        build_photon_table(d, c->mask, ph0, phd, &ph_tab[(size_t)slot * 3 * NB_PH]);
+        build_electron_table(d, c->mask, el0, eld, &el_tab[(size_t)slot * 3 * NB_EL]);
+        x0[slot] = (float)d.x0;
+    };
+    for (int s2 = 0; s2 < nslot; ++s2) build_slot(s2, mat_of_slot[s2]);
+    for (size_t l = 0; l < c->layers.size(); ++l) build_slot(MAX_PMAT + (int)l, c->layers[l].material);
+    for (int i = 0; i < NB_PH; ++i) {
+        double m = 0;
+        for (int s2 = 0; s2 < nslot; ++s2) m = std::max(m, (double)rho_max[s2] * ph_tab[(size_t)s2 * 3 * NB_PH + i]);
+        maj[i] = (float)(m * (1.0 + 1e-5));   // margin over the FP32 rounding of rho * mu
+    }
+
+    // source
+    const int nbins = std::max<int>(1, (int)c->weights.size());
+    std::vector<float> sp_lo(nbins, 0), sp_hi(nbins, 0), sp_prob(nbins, 1), ap_prob, ap_a, ap_b;
+    std::vector<int> sp_alias(nbins, 0), ap_alias;
+    if (!c->weights.empty()) {
+        std::vector<double> w(c->weights.begin(), c->weights.end());
+        build_alias(w, sp_prob, sp_alias);
+        for (int i = 0; i < nbins; ++i) { sp_lo[i] = c->edges[i]; sp_hi[i] = c->edges[i + 1]; }
+    }
+    const int nseg = std::max(1, c->n_seg), npair = std::max(1, c->n_pairs);
+    ap_a.assign((size_t)nseg * npair, 0.0f);
+    ap_b.assign((size_t)nseg * npair, 0.0f);
+    ap_prob.assign((size_t)nseg * npair, 1.0f);
+    ap_alias.assign((size_t)nseg * npair, 0);
+    std::vector<unsigned long long> seg_end(nseg, ~0ull);
+    if (c->n_seg > 0) {
+        ap_a = c->ap_a;
+        ap_b = c->ap_b;
+        unsigned long long cum = 0;
+        for (int s2 = 0; s2 < c->n_seg; ++s2) {
+            std::vector<double> wv(c->n_pairs);
+            for (int k = 0; k < c->n_pairs; ++k) wv[k] = (double)c->ap_b[s2 * c->n_pairs + k] - c->ap_a[s2 * c->n_pairs + k];
+            std::vector<float> pr;
+            std::vector<int> al;
+            build_alias(wv, pr, al);
+            std::copy(pr.begin(), pr.end(), ap_prob.begin() + (size_t)s2 * c->n_pairs);
+            std::copy(al.begin(), al.end(), ap_alias.begin() + (size_t)s2 * c->n_pairs);
+            cum += c->seg_hist[s2];
+            seg_end[s2] = c->n_seg > 1 ? cum : ~0ull;
+        }
+    }
+
+    // uploads
+    auto up = [&](const Region &r, const void *src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(w + r.off, src, n, hipMemcpyHostToDevice, s);
+    };
+    HIPCHK(up(L.vox, vox.data(), nvox * 4));
+    HIPCHK(up(L.ph_tab, ph_tab.data(), ph_tab.size() * 4));
+    HIPCHK(up(L.ph_maj, maj.data(), maj.size() * 4));
+    HIPCHK(up(L.el_tab, el_tab.data(), el_tab.size() * 4));
+    HIPCHK(up(L.sp_lo, sp_lo.data(), nbins * 4));
+    HIPCHK(up(L.sp_hi, sp_hi.data(), nbins * 4));
+    HIPCHK(up(L.sp_prob, sp_prob.data(), nbins * 4));
+    HIPCHK(up(L.sp_alias, sp_alias.data(), nbins * 4));
+    HIPCHK(up(L.ap_a, ap_a.data(), ap_a.size() * 4));
+    HIPCHK(up(L.ap_b, ap_b.data(), ap_b.size() * 4));
+    HIPCHK(up(L.ap_prob, ap_prob.data(), ap_prob.size() * 4));
+    HIPCHK(up(L.ap_alias, ap_alias.data(), ap_alias.size() * 4));
+    HIPCHK(up(L.seg_end, seg_end.data(), seg_end.size() * 8));
+    if (c->n_phsp) HIPCHK(up(L.phsp, c->phsp.data(), c->phsp.size() * 4));
+    HIPCHK(launch_zero(w + L.ctl.off, L.ctl.bytes, s));
+    HIPCHK(launch_zero(w + L.img.off, L.img.bytes, s));
+    HIPCHK(launch_zero(w + L.sum.off, L.sum.bytes, s));
+    HIPCHK(launch_zero(w + L.sum2.off, L.sum2.bytes, s));
+    HIPCHK(launch_zero(w + L.led.off, L.led.bytes, s));
+    HIPCHK(hipStreamSynchronize(s));   // host vectors go out of scope
+
+    // parameters
+    Params &P = c->P;
+    P = Params{};
+    char *q = w + L.queues.off;
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < NQ; ++k) {
+            Queue &Q = c->qs[b][k];
+            const size_t n = L.cap[k];
+            float **fp[7] = {&Q.x, &Q.y, &Q.z, &Q.u, &Q.v, &Q.w, &Q.E};
+            for (int f = 0; f < 7; ++f) { *fp[f] = (float *)q; q += n * 4; }
+            uint32_t **up5[5] = {&Q.hist, &Q.plo, &Q.phi, &Q.draw, &Q.flags};
+            for (int f = 0; f < 5; ++f) { *up5[f] = (uint32_t *)q; q += n * 4; }
+        }
+    for (int k = 0; k < NQ; ++k) P.cap[k] = L.cap[k];
+    char *ctl = w + L.ctl.off;
+    P.cnt = (uint32_t *)(ctl + CTL_CNT);
+    P.heads = P.cnt + 2 * NQ;
+    P.err = (uint32_t *)(ctl + CTL_ERR);
+    P.stats = (unsigned long long *)(ctl + CTL_STATS);
+    P.nx = c->nx; P.ny = c->ny; P.nz = c->nz;
+    P.dx = c->spacing[0]; P.dy = c->spacing[1]; P.dz = c->spacing[2];
+    P.idx = 1.0f / P.dx; P.idy = 1.0f / P.dy; P.idz = 1.0f / P.dz;
+    P.Lx = (float)((double)c->nx * c->spacing[0]);
+    P.Ly = (float)((double)c->ny * c->spacing[1]);
+    P.Lz = (float)((double)c->nz * c->spacing[2]);
+    P.ox = c->origin[0]; P.oy = c->origin[1]; P.oz = c->origin[2];
+    P.chord = P.Lx + P.Ly + P.Lz + 1.0f;
+    P.ddx = c->spacing[0]; P.ddy = c->spacing[1]; P.ddz = c->spacing[2];
+    P.smin_ph = SKIN * std::min(c->spacing[0], std::min(c->spacing[1], c->spacing[2]));
+    P.vox = (const uint32_t *)(w + L.vox.off);
+    P.nl = (int)c->layers.size();
+    P.scoring = c->scoring;
+    double z = 0;
+    P.zl[0] = 0.0f;
+    for (int l = 0; l < P.nl; ++l) {
+        z += c->layers[l].thickness;
+        P.zl[l + 1] = (float)z;
+        P.lrho[l] = c->layers[l].density;
+        P.lsmin[l] = SKIN * c->layers[l].thickness;
+    }
+    for (int l = P.nl + 1; l <= MAX_LAYERS; ++l) P.zl[l] = (float)z;
+    P.zback = (float)z;
+    P.front_z = c->front_z;
+    P.hx = (float)(0.5 * c->npx_u * (double)c->pitch_u);
+    P.hy = (float)(0.5 * c->npx_v * (double)c->pitch_v);
+    P.npx_u = c->npx_u; P.npx_v = c->npx_v;
+    P.pitch_u = c->pitch_u; P.pitch_v = c->pitch_v;
+    P.ipu = 1.0f / c->pitch_u; P.ipv = 1.0f / c->pitch_v;
+    P.s_pix = 0.5f * std::min(c->pitch_u, c->pitch_v);
+    P.ph_to_epid_z = (float)((double)c->front_z - (double)c->origin[2]);
+    P.ph_tab = (const float *)(w + L.ph_tab.off);
+    P.ph_maj = (const float *)(w + L.ph_maj.off);
+    P.el_tab = (const float *)(w + L.el_tab.off);
+    P.ph_lnE0 = (float)ph0; P.ph_idl = (float)(1.0 / phd);
+    P.el_lnT0 = (float)el0; P.el_idl = (float)(1.0 / eld);
+    for (int i = 0; i < MAX_PMAT + MAX_LAYERS; ++i) P.el_x0[i] = x0[i];
+    P.nmat_ph = nslot;
+    P.coupled = c->coupled;
+    P.mask = c->mask;
+    P.pcut = c->pcut;
+    P.ecut = c->ecut;
+    P.beam_kind = c->beam.kind;
+    for (int a = 0; a < 3; ++a) P.src[a] = c->beam.src[a];
+    P.iso_z = c->beam.iso_z;
+    P.nbins = nbins;
+    P.sp_lo = (const float *)(w + L.sp_lo.off);
+    P.sp_hi = (const float *)(w + L.sp_hi.off);
+    P.sp_prob = (const float *)(w + L.sp_prob.off);
+    P.sp_alias = (const int *)(w + L.sp_alias.off);
+    P.n_seg = nseg;
+    P.n_pairs = npair;
+    P.leaf_w = c->leaf_w;
+    P.y0 = c->y0;
+    P.ap_a = (const float *)(w + L.ap_a.off);
+    P.ap_b = (const float *)(w + L.ap_b.off);
+    P.ap_prob = (const float *)(w + L.ap_prob.off);
+    P.ap_alias = (const int *)(w + L.ap_alias.off);
+    P.seg_end = (const unsigned long long *)(w + L.seg_end.off);
+    P.phsp = c->n_phsp ? (const float *)(w + L.phsp.off) : nullptr;
+    P.n_phsp = c->n_phsp;
+    P.tally_mode = c->tally_mode;
+    P.npix = (uint32_t)((size_t)c->npx_u * c->npx_v);
+    P.img = w + L.img.off;
+    P.rec_pix = (uint32_t *)(w + L.rec_pix.off);
+    P.rec_e = (float *)(w + L.rec_e.off);
+    P.rec_cap = L.rec_cap;
+    P.sum = (double *)(w + L.sum.off);
+    P.sum2 = (double *)(w + L.sum2.off);
+    P.diag = c->diag;
+    P.led = (double *)(w + L.led.off);
+    P.ein = (double *)(w + L.ein.off);
+    P.key0 = (uint32_t)c->seed;
+    P.key1 = (uint32_t)(c->seed >> 32);
+    P.run_batches = 1;
+    P.run_n = 1;
+
+    // workgroups per CU each transport kernel can keep resident
+    for (int k = 0; k < NQ; ++k) {
+        const size_t lds = lds_bytes(k, P);
+        c->occ[k] = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / std::max<size_t>(lds, 1)));
+    }
+    c->ws = w;
+    c->ws_bytes = bytes;
+    c->lay = L;
+    c->bound = true;
+    c->n_total = 0;
+    c->b_total = 0;
+    c->launches = 0;
+    c->queue_peak = 0;
+    return EPIDMC_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// run
+// ---------------------------------------------------------------------------------
+static epidmc_status check_error_word(epidmc_ctx *c, uint32_t e)
+{
+    if (e & ERR_NAN) return fail(c, EPIDMC_E_NAN, "non-finite particle energy on the device");
+    if (e & ERR_QUEUE) return fail(c, EPIDMC_E_OVERFLOW, "particle queue overflow: lower max_chunk_histories");
+    if (e & ERR_STEPS) return fail(c, EPIDMC_E_OVERFLOW, "electron step limit exceeded");
+    if (e & ERR_FIXED) return fail(c, EPIDMC_E_OVERFLOW, "fixed-point tally overflow");
+    return EPIDMC_OK;
+}
+
+// histories of variance batch b of a run [first, first+n) split into B batches: batch of h
+// is (h - first) * B / n, so batch b starts at first + ceil(b n / B)
+static uint64_t batch_start(uint64_t first, uint64_t n, int B, uint64_t b)
+{
+    return first + (b * n + (uint64_t)B - 1) / (uint64_t)B;
+}
+
+static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStream_t s)
+{
+    Params P = c->P;
+    P.h0 = h0;
+    P.h1 = h1;
+    uint32_t *cnt = P.cnt;
+    HIPCHK(launch_zero(cnt, 64, s));
+    // the source appends into buffer 0
+    auto use = [&](int cur) {
+        for (int k = 0; k < NQ; ++k) { P.in[k] = c->qs[cur][k]; P.out[k] = c->qs[1 - cur][k]; }
+        P.cnt_in = cnt + cur * NQ;
+        P.cnt_out = cnt + (1 - cur) * NQ;
+    };
+    use(1);
+    HIPCHK(launch_source(P, s));
+    ++c->launches;
+    int cur = 0;
+    bool timed[NQ] = {false, false, false, false};
+    for (int pass = 0; pass < 100000; ++pass) {
+        HIPCHK(hipMemcpyAsync(c->host, cnt + cur * NQ, NQ * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(c->host + NQ, P.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < NQ; ++k)
+            if (timed[k]) {
+                float ms = 0.0f;
+                HIPCHK(hipEventElapsedTime(&ms, c->ev[0][k], c->ev[1][k]));
+                c->kernel_ms[k] += ms;
+                ++c->kernel_launches[k];
+                timed[k] = false;
+            }
+        uint32_t n[NQ];
+        std::memcpy(n, c->host, sizeof n);
+        if (c->host[NQ] & (ERR_QUEUE | ERR_NAN | ERR_STEPS)) return check_error_word(c, c->host[NQ]);
+        bool any = false;
+        for (int k = 0; k < NQ; ++k) {
+            any |= n[k] > 0;
+            c->queue_peak = std::max<uint64_t>(c->queue_peak, n[k]);
+        }
+        if (!any) break;
+        // clear the other buffer's fill counts and all consume heads
+        HIPCHK(launch_zero(cnt + (1 - cur) * NQ, NQ * sizeof(uint32_t), s));
+        HIPCHK(launch_zero(cnt + 2 * NQ, NQ * sizeof(uint32_t), s));
+        use(cur);
+        for (int k = 0; k < NQ; ++k) {
+            if (!n[k]) continue;
+            const uint64_t per_block = (uint64_t)WG * ITEMS_PER_LANE;
+            const uint64_t want = (n[k] + per_block - 1) / per_block;
+            const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * c->occ[k]));
+            if (c->prof) HIPCHK(hipEventRecord(c->ev[0][k], s));
+            HIPCHK(launch_transport(k, P, blocks, s));
+            if (c->prof) {
+                HIPCHK(hipEventRecord(c->ev[1][k], s));
+                timed[k] = true;
+            }
+            ++c->launches;
+        }
+        cur = 1 - cur;
+    }
+    if (c->tally_mode == 2) {
+        HIPCHK(hipMemcpyAsync(c->host, cnt + 3 * NQ, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const uint32_t nrec = std::min(c->host[0], c->lay.rec_cap);
+        const uint32_t nimg = (uint32_t)((size_t)c->lay.ring * P.npix);
+        HIPCHK(launch_kahan_reduce(P, nrec, nimg, (uint32_t *)(c->ws + c->lay.k_count.off),
+                                   (uint32_t *)(c->ws + c->lay.k_cursor.off), (uint32_t *)(c->ws + c->lay.k_bsum.off),
+                                   (float *)(c->ws + c->lay.k_sorted.off), s));
+        HIPCHK(launch_zero(cnt + 3 * NQ, 4, s));
+    }
+    if (c->diag) {
+        HIPCHK(launch_diag_check(P, (uint32_t)(h1 - h0), (unsigned long long *)(c->ws + c->lay.ctl.off + CTL_DIAG),
+                                 (double *)(c->ws + c->lay.ctl.off + CTL_DIAG + 8), s));
+    }
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first, uint64_t n, void *stream)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(c->bound, EPIDMC_E_NOT_READY, "workspace not bound (call epidmc_bind_workspace after the last set_*)");
+    REQUIRE(n >= (uint64_t)c->batches, EPIDMC_E_ARG, "need at least one history per variance batch");
+    REQUIRE(first + n <= (1ull << 32) && first + n > first, EPIDMC_E_RANGE, "history ids must stay below 2^32");
+    if (c->n_seg > 1 && c->n_phsp == 0) {
+        uint64_t tot = 0;
+        for (uint64_t v : c->seg_hist) tot += v;
+        REQUIRE(first + n <= tot, EPIDMC_E_RANGE, "histories beyond the segments' total");
+    }
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int B = c->batches;
+    const int ring = c->lay.ring;
+    c->P.run_first = first;
+    c->P.run_n = n;
+    c->P.run_batches = B;
+    c->P.ring = ring;
+    uint64_t h = first;
+    uint64_t next_fold = 0;   // first batch not yet folded
+    while (h < first + n) {
+        // a chunk ends at the chunk cap, and never spans more than `ring` batches
+        uint64_t h1 = std::min(first + n, h + c->lay.chunk);
+        const uint64_t b_first = (h - first) * (uint64_t)B / n;
+        const uint64_t b_lim = b_first + (uint64_t)ring;   // batches [b_first, b_lim) may be in flight
+        if (b_lim < (uint64_t)B) h1 = std::min(h1, batch_start(first, n, B, b_lim));
+        epidmc_status st = run_chunk(c, h, h1, s);
+        if (st != EPIDMC_OK) return st;
+        // fold the batches that are complete
+        const uint64_t b_done = (h1 >= first + n) ? (uint64_t)B : (h1 - first) * (uint64_t)B / n;
+        // fold the complete batches, in batch order (an incomplete batch keeps its slot)
+        while (next_fold < b_done) {
+            int slots[MAX_SLOTS];
+            double nbs[MAX_SLOTS];
+            int k = 0;
+            for (; k < MAX_SLOTS && next_fold < b_done; ++k, ++next_fold) {
+                slots[k] = (int)(next_fold % (uint64_t)ring);
+                nbs[k] = (double)(batch_start(first, n, B, next_fold + 1) - batch_start(first, n, B, next_fold));
+            }
+            HIPCHK(launch_fold(c->P, slots, nbs, k, s));
+        }
+        h = h1;
+    }
+    HIPCHK(hipMemcpyAsync(c->host, c->P.err, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    epidmc_status st = check_error_word(c, c->host[0]);
+    if (st != EPIDMC_OK) return st;
+    c->n_total += (double)n;
+    c->b_total += (double)B;
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_read_image(epidmc_ctx *c, double *mean, double *var, void *stream)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(c->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    REQUIRE(mean && var, EPIDMC_E_ARG, "null output");
+    REQUIRE(c->n_total > 0, EPIDMC_E_NOT_READY, "no histories run");
+    HIPCHK(launch_image(c->P, c->n_total, c->b_total, mean, var, (hipStream_t)stream));
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_sigma_bar(epidmc_ctx *c, double thr, void *stream, double *out)
+{
+    if (!c || !out) return EPIDMC_E_ARG;
+    REQUIRE(c->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    REQUIRE(c->n_total > 0, EPIDMC_E_NOT_READY, "no histories run");
+    REQUIRE(thr >= 0 && thr <= 1, EPIDMC_E_ARG, "threshold fraction in [0,1]");
+    hipStream_t s = (hipStream_t)stream;
+    double *d = (double *)(c->ws + c->lay.ctl.off + CTL_SIGMA);
+    HIPCHK(launch_sigma_bar(c->P, c->n_total, c->b_total, thr, d, s));
+    HIPCHK(hipMemcpyAsync(c->host, d, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::memcpy(out, c->host, 8);
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_run_until(epidmc_ctx *c, double target, double thr, uint64_t first, uint64_t step,
+                                          uint64_t max_hist, void *stream, uint64_t *done, double *sb)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(target > 0 && std::isfinite(target), EPIDMC_E_ARG, "target must be > 0");
+    REQUIRE(step >= (uint64_t)c->batches && max_hist >= step, EPIDMC_E_ARG, "step >= batches and max >= step");
+    uint64_t n = 0;
+    double sig = INFINITY;
+    while (n + step <= max_hist) {
+        epidmc_status st = epidmc_run(c, first + n, step, stream);
+        if (st != EPIDMC_OK) return st;
+        n += step;
+        st = epidmc_sigma_bar(c, thr, stream, &sig);
+        if (st != EPIDMC_OK) return st;
+        if (sig <= target) break;
+    }
+    if (done) *done = n;
+    if (sb) *sb = sig;
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_reset_tally(epidmc_ctx *c, void *stream)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(c->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_zero(c->ws + c->lay.img.off, c->lay.img.bytes, s));
+    HIPCHK(launch_zero(c->ws + c->lay.sum.off, c->lay.sum.bytes, s));
+    HIPCHK(launch_zero(c->ws + c->lay.sum2.off, c->lay.sum2.bytes, s));
+    HIPCHK(launch_zero(c->ws + c->lay.ctl.off, c->lay.ctl.bytes, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->n_total = 0;
+    c->b_total = 0;
+    c->launches = 0;
+    c->queue_peak = 0;
+    for (int k = 0; k < NQ; ++k) { c->kernel_ms[k] = 0; c->kernel_launches[k] = 0; }
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_get_counters(epidmc_ctx *c, epidmc_counters *out)
+{
+    if (!c || !out) return EPIDMC_E_ARG;
+    REQUIRE(c->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    std::vector<unsigned char> buf(CTL_BYTES);
+    HIPCHK(hipMemcpy(buf.data(), c->ws + c->lay.ctl.off, CTL_BYTES, hipMemcpyDeviceToHost));
+    unsigned long long st[S_NSTAT];
+    std::memcpy(st, buf.data() + CTL_STATS, sizeof st);
+    uint32_t err;
+    std::memcpy(&err, buf.data() + CTL_ERR, 4);
+    unsigned long long mbits;
+    double sums[2];
+    std::memcpy(&mbits, buf.data() + CTL_DIAG, 8);
+    std::memcpy(sums, buf.data() + CTL_DIAG + 8, 16);
+    epidmc_counters &o = *out;
+    o = epidmc_counters{};
+    o.histories = (uint64_t)c->n_total;
+    o.n_compton = st[S_COMPTON]; o.n_photo = st[S_PHOTO]; o.n_pair = st[S_PAIR];
+    o.n_annih = st[S_ANNIH]; o.n_brems = st[S_BREMS]; o.n_moller = st[S_MOLLER];
+    o.woodcock_steps = st[S_WOODCOCK];
+    o.epid_photon_steps = st[S_EPID_PH_STEPS];
+    o.e_steps_phantom = st[S_ESTEP_P];
+    o.e_steps_epid = st[S_ESTEP_E];
+    o.photon_epid_entries = st[S_EPID_ENTRIES];
+    o.unscattered_at_epid = st[S_UNSCAT];
+    o.tally_deposits = st[S_TALLY];
+    for (int k = 0; k < 4; ++k) {
+        o.queue_items[k] = st[S_ITEMS0 + k];
+        o.lane_iters[k] = st[S_LANE0 + k];
+        o.wave_iters[k] = st[S_WAVE0 + k];
+    }
+    o.launches = c->launches;
+    o.queue_peak = c->queue_peak;
+    o.error_word = err;
+    double mx;
+    std::memcpy(&mx, &mbits, 8);
+    o.max_ledger_resid = mx;
+    o.e_in = sums[0];
+    o.e_deposited = sums[1];
+    o.e_escaped = 0;
+    for (int k = 0; k < NQ; ++k) {
+        o.kernel_ms[k] = c->kernel_ms[k];
+        o.kernel_launches[k] = c->kernel_launches[k];
+    }
+    return check_error_word(c, err);
+}
+
+extern "C" epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *ctr, uint32_t *out, uint64_t n, void *stream)
+{
+    if (!c || !ctr || !out || n == 0) return EPIDMC_E_ARG;
+    Params P{};
+    P.key0 = (uint32_t)c->seed;
+    P.key1 = (uint32_t)(c->seed >> 32);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(launch_dbg_philox(P, ctr, out, n, (hipStream_t)stream));
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_debug_sample(epidmc_ctx *c, int kind, double p0, double p1, double p2, float *out,
+                                             uint64_t n, void *stream)
+{
+    if (!c || !out || n == 0 || kind < 0 || kind > 4) return EPIDMC_E_ARG;
+    Params P = c->P;
+    if (kind == 4) REQUIRE(c->bound, EPIDMC_E_NOT_READY, "source probe needs a bound workspace");
+    P.key0 = (uint32_t)c->seed;
+    P.key1 = (uint32_t)(c->seed >> 32);
+    if (kind == 0) REQUIRE(p0 > 0 && p0 <= 50, EPIDMC_E_RANGE, "energy in (0, 50]");
+    if (kind == 1) REQUIRE(p0 > 2 * WCUT && p0 <= 50, EPIDMC_E_RANGE, "Moller needs T > 0.4 MeV");
+    if (kind == 2) REQUIRE(p0 > KCUT && p0 <= 50, EPIDMC_E_RANGE, "bremsstrahlung needs T > 10 keV");
+    if (kind == 3) REQUIRE(p0 > 0 && p1 >= 0 && p2 > 0, EPIDMC_E_RANGE, "scattering arguments");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(launch_dbg_sample(P, kind, (float)p0, (float)p1, (float)p2, out, n, (hipStream_t)stream));
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_debug_table(epidmc_ctx *c, int kind, int index, const float *E, float *out, uint64_t n,
+                                            void *stream)
+{
+    if (!c || !E || !out || n == 0) return EPIDMC_E_ARG;
+    REQUIRE(c->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    REQUIRE(kind >= 0 && kind <= 2 && index >= 0 && index < MAX_PMAT + MAX_LAYERS, EPIDMC_E_ARG, "table kind/index");
+    HIPCHK(launch_dbg_table(c->P, kind, index, E, out, n, (hipStream_t)stream));
+    return EPIDMC_OK;
+}

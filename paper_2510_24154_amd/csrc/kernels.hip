@@ -1,0 +1,1155 @@
+// kernels.hip -- gfx950 kernels of the EPID transit Monte Carlo engine.
+//
+// Transport runs as a loop of queue passes.  Each pass launches one persistent kernel
+// per non-empty queue (photons / electrons x phantom / EPID); a wave keeps its 64 lanes
+// busy by refilling idle lanes from its queue, advances every lane by one step per loop
+// iteration, and appends secondaries and region changes to next-pass queues with one
+// atomic per wave.  Cross-section tables are staged in LDS once per workgroup.
+//
+// Physics per step (the paper's physics class, Sec. 2.1.2, with the model readings
+// documented in the design doc):
+//   photons in the phantom: Woodcock delta tracking against a per-energy majorant;
+//   photons in the EPID: exact slab-by-slab tracking (Sec. 2.1.3);
+//   interactions: Compton (Klein-Nishina, Butcher-Messel composition-rejection),
+//     photoelectric absorption, pair production;
+//   electrons: Class II condensed history -- steps limited by the sampled distance to a
+//     hard event, a 10% energy-loss cap, the cell boundary and half a pixel in the
+//     scoring layer; CSDA loss through the restricted range table; random-hinge
+//     Gaussian multiple scattering; hard Moller and bremsstrahlung events.
+#include "device.hpp"
+
+namespace epidmc {
+
+#define MEC2F 0.51099895f
+#define TWO_PI_F 6.28318530717958647692f
+
+struct Local {   // per-lane work counters
+    unsigned compton, photo, pair, annih, brems, moller, steps, entries, unscat, tally, items;
+};
+
+__device__ __forceinline__ void zero(Local &L) { L = Local{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}; }
+
+__device__ __forceinline__ void flush_stats(const Params &P, const Local &L, int step_stat, int q,
+                            unsigned long long lane_iters, unsigned long long wave_iters)
+{
+    __shared__ unsigned long long s[16];
+    if (threadIdx.x < 16) s[threadIdx.x] = 0;
+    __syncthreads();
+    const unsigned v[11] = {L.compton, L.photo, L.pair, L.annih, L.brems, L.moller, L.steps, L.entries,
+                            L.unscat, L.tally, L.items};
+#pragma unroll
+    for (int k = 0; k < 11; ++k)
+        if (v[k]) atomicAdd(&s[k], (unsigned long long)v[k]);
+    if (lane_id() == 0) {
+        atomicAdd(&s[11], lane_iters);
+        atomicAdd(&s[12], wave_iters);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int map[11] = {S_COMPTON, S_PHOTO, S_PAIR, S_ANNIH, S_BREMS, S_MOLLER, step_stat,
+                             S_EPID_ENTRIES, S_UNSCAT, S_TALLY, S_ITEMS0 + q};
+#pragma unroll
+        for (int k = 0; k < 11; ++k)
+            if (s[k]) atomicAdd(&P.stats[map[k]], s[k]);
+        if (s[11]) atomicAdd(&P.stats[S_LANE0 + q], s[11]);
+        if (s[12]) atomicAdd(&P.stats[S_WAVE0 + q], s[12]);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// placement of a particle given in the phantom frame (source particles, particles that
+// leave the phantom box): inside the box it stays; otherwise it flies on a straight line
+// to the box (if its ray enters it) or to the EPID front face within the image area, or
+// it escapes.  Returns 0 phantom, 1 EPID (p converted to the EPID frame), 2 escaped.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ int vacuum_phantom_frame(const Params &P, Part &p)
+{
+    if (in_phantom(P, p.x, p.y, p.z)) return 0;
+    const float pos[3] = {p.x, p.y, p.z}, dir[3] = {p.u, p.v, p.w}, L3[3] = {P.Lx, P.Ly, P.Lz};
+    float tin = -INFINITY, tout = INFINITY;
+    int ain = -1;
+    bool hit = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (dir[a] != 0.0f) {
+            const float inv = 1.0f / dir[a];
+            float t1 = (0.0f - pos[a]) * inv, t2 = (L3[a] - pos[a]) * inv;
+            if (t1 > t2) { const float t = t1; t1 = t2; t2 = t; }
+            if (t1 > tin) { tin = t1; ain = a; }
+            tout = fminf(tout, t2);
+        } else if (!(pos[a] >= 0.0f && pos[a] < L3[a])) {
+            hit = false;
+        }
+    }
+    if (hit && tin > 0.0f && tin < tout) {
+        // the entry point, clamped inside the half-open box; the entry face coordinate exact
+        float q0 = fminf(fmaxf(fmaf(tin, p.u, p.x), 0.0f), __uint_as_float(__float_as_uint(P.Lx) - 1u));
+        float q1 = fminf(fmaxf(fmaf(tin, p.v, p.y), 0.0f), __uint_as_float(__float_as_uint(P.Ly) - 1u));
+        float q2 = fminf(fmaxf(fmaf(tin, p.w, p.z), 0.0f), __uint_as_float(__float_as_uint(P.Lz) - 1u));
+        if (ain == 0) q0 = p.u > 0.0f ? 0.0f : __uint_as_float(__float_as_uint(P.Lx) - 1u);
+        if (ain == 1) q1 = p.v > 0.0f ? 0.0f : __uint_as_float(__float_as_uint(P.Ly) - 1u);
+        if (ain == 2) q2 = p.w > 0.0f ? 0.0f : __uint_as_float(__float_as_uint(P.Lz) - 1u);
+        p.x = q0; p.y = q1; p.z = q2;
+        return 0;
+    }
+    if (p.w > 0.0f) {
+        const float t = (P.ph_to_epid_z - p.z) / p.w;
+        const float xg = fmaf(t, p.u, p.x) + P.ox, yg = fmaf(t, p.v, p.y) + P.oy;
+        if (xg >= -P.hx && xg < P.hx && yg >= -P.hy && yg < P.hy) {
+            p.x = xg; p.y = yg; p.z = 0.0f;
+            return 1;
+        }
+    }
+    return 2;
+}
+
+// hand a particle (position in the frame of `region`) to its next queue, or let it escape
+__device__ __forceinline__ void place(const Params &P, int region, Part &c, Local &L, Stages S = Stages{nullptr, nullptr})
+{
+    const bool photon = (c.flags & F_TYPE) == 0;
+    int r = region;
+    if (region == 0) {
+        r = vacuum_phantom_frame(P, c);
+        if (r == 1 && photon) {
+            ++L.entries;
+            if (c.flags & F_UNSCAT) ++L.unscat;
+        }
+    } else {
+        if (epid_layer(P, c.x, c.y, c.z) < 0) r = 2;
+    }
+    if (r == 2) {
+        ledger(P, c.hist, (double)c.E);
+        return;
+    }
+    if (r == 1 && photon) {
+        const int l = max(epid_layer(P, c.x, c.y, c.z), 0);
+        c.flags = (c.flags & ~F_LAYER_MASK) | ((uint32_t)l << F_LAYER_SHIFT);
+    }
+    const int kind = (r == 0) ? (photon ? QGP : QEP) : (photon ? QGE : QEE);
+    // appends are grouped by kind so each call ballots only the lanes of that kind
+    append(P, S, QGP, kind == QGP, c);
+    append(P, S, QEP, kind == QEP, c);
+    append(P, S, QGE, kind == QGE, c);
+    append(P, S, QEE, kind == QEE, c);
+}
+
+// deposit at a point of `region` (phantom: ledger only; EPID: tallied in the scoring layer)
+__device__ __forceinline__ void deposit_point(const Params &P, int region, const Part &at, float e, Local &L)
+{
+    ledger(P, at.hist, (double)e);
+    if (region == 1) {
+        unsigned n = 0;
+        deposit_epid_point(P, at, e, n);
+        L.tally += n;
+    }
+}
+
+// a new photon at the parent's position
+__device__ __forceinline__ void emit_photon(const Params &P, int region, Part &parent, float E, float u, float v, float w,
+                            Local &L, Stages S = Stages{nullptr, nullptr})
+{
+    Part c;
+    make_child(parent, c, P, 0u);
+    c.x = parent.x; c.y = parent.y; c.z = parent.z;
+    c.u = u; c.v = v; c.w = w;
+    c.E = E;
+    if (E < P.pcut) {
+        deposit_point(P, region, c, E, L);
+        return;
+    }
+    place(P, region, c, L, S);
+}
+
+// two back-to-back photons of m c^2 from a positron at rest
+__device__ __forceinline__ void annihilate(const Params &P, int region, Part &pos, Local &L, Stages S = Stages{nullptr, nullptr})
+{
+    const float4 r = rnd4(pos, P);
+    const float ct = 2.0f * r.x - 1.0f, st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    float sp, cp;
+    __sincosf(TWO_PI_F * r.y, &sp, &cp);
+    ++L.annih;
+    ledger(P, pos.hist, -2.0 * (double)MEC2F);
+    emit_photon(P, region, pos, MEC2F, st * cp, st * sp, ct, L, S);
+    emit_photon(P, region, pos, MEC2F, -st * cp, -st * sp, -ct, L, S);
+}
+
+// a new electron (type 1) or positron (type 2) at the parent's position
+__device__ __forceinline__ void emit_electron(const Params &P, int region, Part &parent, float T, uint32_t type, float u, float v,
+                              float w, Local &L, Stages S = Stages{nullptr, nullptr})
+{
+    Part c;
+    make_child(parent, c, P, type);
+    c.x = parent.x; c.y = parent.y; c.z = parent.z;
+    c.u = u; c.v = v; c.w = w;
+    c.E = T;
+    if (!P.coupled || T < P.ecut) {
+        deposit_point(P, region, c, T, L);
+        if (type == 2u) annihilate(P, region, c, L, S);
+        return;
+    }
+    place(P, region, c, L, S);
+}
+
+// ---------------------------------------------------------------------------------
+// samplers
+// ---------------------------------------------------------------------------------
+// Klein-Nishina eps = E'/E by the Butcher-Messel split of (1/eps + eps) into a 1/eps part and
+// an eps part, with the rejection function 1 - eps sin^2/(1 + eps^2).  Also returns the
+// azimuth uniform of the accepted trial.
+__device__ __forceinline__ float kn_sample(const Params &P, Part &p, float E, float &t_out, float &phi_u)
+{
+    const float k = E * (1.0f / MEC2F);
+    const float e0 = 1.0f / fmaf(2.0f, k, 1.0f);
+    const float a1 = __logf(fmaf(2.0f, k, 1.0f));
+    const float e02 = e0 * e0;
+    const float a2 = 0.5f * (1.0f - e02);
+    float eps = 1.0f, t = 0.0f;
+    for (int trial = 0; trial < 10000; ++trial) {
+        const float4 r = rnd4(p, P);
+        eps = (r.x * (a1 + a2) < a1) ? __expf(-a1 * r.y) : sqrtf(fmaf(1.0f - e02, r.y, e02));
+        eps = fminf(fmaxf(eps, e0), 1.0f);
+        t = (1.0f - eps) / (k * eps);
+        const float s2 = t * (2.0f - t);
+        const float g = 1.0f - eps * s2 / fmaf(eps, eps, 1.0f);
+        phi_u = r.w;
+        if (r.z < g) break;
+    }
+    t_out = fminf(t, 2.0f);
+    return eps;
+}
+
+// Moller energy transfer W in [WCUT, T/2]: 1/eps^2 proposal, rejection by the rest of the
+// Moller bracket, bounded by 2 + c1/4 on the interval
+__device__ __forceinline__ float moller_sample(const Params &P, Part &p, float T, float &phi_u)
+{
+    const float ec = (float)WCUT / T;
+    const float g = T * (1.0f / MEC2F) + 1.0f;
+    const float c1 = (g - 1.0f) * (g - 1.0f) / (g * g), c2 = (2.0f * g - 1.0f) / (g * g);
+    const float bound = 2.0f + 0.25f * c1;
+    float eps = ec;
+    for (int trial = 0; trial < 10000; ++trial) {
+        const float4 r = rnd4(p, P);
+        eps = ec / (1.0f - r.x * (1.0f - 2.0f * ec));
+        const float x = eps / (1.0f - eps);
+        const float gf = 1.0f + x * x + c1 * eps * eps - c2 * x;
+        phi_u = r.z;
+        if (r.y * bound < gf) break;
+    }
+    return fminf(fmaxf(eps, ec), 0.5f) * T;
+}
+
+// Highland width (unit charge) for kinetic energy T over x g/cm^2 of radiation length X0
+__device__ __forceinline__ float highland(float T, float x, float X0)
+{
+    if (!(x > 0.0f)) return 0.0f;
+    const float E = T + MEC2F;
+    const float pc2 = T * (T + 2.0f * MEC2F);
+    const float bcp = pc2 / E, b2 = pc2 / (E * E);
+    const float r = x / X0;
+    const float br = fmaxf(0.0f, 1.0f + 0.038f * __logf(r / b2));
+    return 13.6f / bcp * sqrtf(r) * br;
+}
+
+// ---------------------------------------------------------------------------------
+// photon interaction at p inside material table `tab` (3 rows of NB_PH) at node n.
+// Returns true while the photon lives.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ bool photon_interact(const Params &P, int region, Part &p, const float *tab, Node n, float rproc,
+                                Local &L, Stages S = Stages{nullptr, nullptr})
+{
+    const float fc = lerp_tab(tab + NB_PH, n), fcp = lerp_tab(tab + 2 * NB_PH, n);
+    p.flags &= ~F_UNSCAT;
+    const float E = p.E;
+    if (rproc < fc) {
+        ++L.compton;
+        float t, phu;
+        const float eps = kn_sample(P, p, E, t, phu);
+        const float ct = 1.0f - t, st = sqrtf(fmaxf(0.0f, t * (2.0f - t)));
+        float sp, cp;
+        __sincosf(TWO_PI_F * phu, &sp, &cp);
+        const float Ep = eps * E, T = E - Ep;
+        if (P.diag) ledger(P, p.hist, (double)E - (double)Ep - (double)T);
+        // electron: momentum conservation, opposite azimuth
+        float eu = p.u, ev = p.v, ew = p.w;
+        if (T > 0.0f) {
+            const float pe = sqrtf(T * (T + 2.0f * MEC2F));
+            const float cte = fminf(1.0f, (E - Ep * ct) / pe), ste = fminf(1.0f, Ep * st / pe);
+            rotate(eu, ev, ew, cte, ste, -cp, -sp);
+        }
+        rotate(p.u, p.v, p.w, ct, st, cp, sp);
+        p.E = Ep;
+        emit_electron(P, region, p, T, 1u, eu, ev, ew, L, S);
+        if (Ep < P.pcut) {
+            deposit_point(P, region, p, Ep, L);
+            return false;
+        }
+        return true;
+    }
+    if (rproc < fcp) {
+        ++L.photo;
+        emit_electron(P, region, p, E, 1u, p.u, p.v, p.w, L, S);
+        return false;
+    }
+    ++L.pair;
+    const float T = E - 2.0f * MEC2F;
+    const float4 r = rnd4(p, P);
+    const float tm = r.x * T, tp = T - tm;
+    if (P.diag) ledger(P, p.hist, (double)E - (double)tm - (double)tp);
+    emit_electron(P, region, p, tm, 1u, p.u, p.v, p.w, L, S);
+    emit_electron(P, region, p, tp, 2u, p.u, p.v, p.w, L, S);
+    return false;
+}
+
+// ---------------------------------------------------------------------------------
+// source: one thread per history
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_source(Params P)
+{
+    Local L;
+    zero(L);
+    const unsigned long long h = P.h0 + (unsigned long long)blockIdx.x * WG + threadIdx.x;
+    const bool live = h < P.h1;
+    Part p;
+    p.hist = (uint32_t)h;
+    p.plo = 0; p.phi = 0; p.draw = 0;
+    float gx = 0, gy = 0, gz = 0;
+    if (live) {
+        const uint32_t slot = (uint32_t)(((h - P.run_first) * (unsigned long long)P.run_batches / P.run_n) % P.ring);
+        uint32_t type = 0;
+        if (P.n_phsp) {
+            const float *q = P.phsp + 8 * (h % P.n_phsp);
+            gx = q[0]; gy = q[1]; gz = q[2];
+            p.u = q[3]; p.v = q[4]; p.w = q[5];
+            p.E = q[6];
+            type = (uint32_t)q[7];
+        } else {
+            const float4 r = rnd4(p, P);
+            int i = min((int)(r.x * (float)P.nbins), P.nbins - 1);
+            if (r.y >= P.sp_prob[i]) i = P.sp_alias[i];
+            p.E = fmaf(r.z, P.sp_hi[i] - P.sp_lo[i], P.sp_lo[i]);
+            int s = 0;
+            if (P.n_seg > 1) {
+                int lo = 0, hi = P.n_seg - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (h < P.seg_end[mid]) hi = mid; else lo = mid + 1;
+                }
+                s = lo;
+            }
+            const float4 r2 = rnd4(p, P);
+            const int base = s * P.n_pairs;
+            int k = min((int)(r2.x * (float)P.n_pairs), P.n_pairs - 1);
+            if (r2.y >= P.ap_prob[base + k]) k = P.ap_alias[base + k];
+            const float a = P.ap_a[base + k], b = P.ap_b[base + k];
+            const float x = fmaf(r2.z, b - a, a);
+            const float y = fmaf((float)k + r2.w, P.leaf_w, P.y0);
+            if (P.beam_kind == 0) {
+                gx = x; gy = y; gz = P.src[2];
+                p.u = 0.0f; p.v = 0.0f; p.w = 1.0f;
+            } else {
+                const float dx = x - P.src[0], dy = y - P.src[1], dz = P.iso_z - P.src[2];
+                const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+                gx = P.src[0]; gy = P.src[1]; gz = P.src[2];
+                p.u = dx * inv; p.v = dy * inv; p.w = dz * inv;
+            }
+        }
+        p.flags = (slot << F_SLOT_SHIFT) | type | (type == 0 ? F_UNSCAT : 0u);
+        if (P.diag) P.ein[h - P.h0] = (double)p.E;
+        p.x = gx - P.ox; p.y = gy - P.oy; p.z = gz - P.oz;
+        // a source particle that starts inside the box is in the phantom
+        if (in_phantom(P, p.x, p.y, p.z)) {
+            const bool photon = type == 0;
+            qappend(P, QGP, photon, p);
+            qappend(P, QEP, !photon, p);
+        } else {
+            place(P, 0, p, L);
+        }
+    }
+    // counters of direct hits on the EPID
+    if (L.entries) atomicAdd(&P.stats[S_EPID_ENTRIES], (unsigned long long)L.entries);
+    if (L.unscat) atomicAdd(&P.stats[S_UNSCAT], (unsigned long long)L.unscat);
+}
+
+// ---------------------------------------------------------------------------------
+// photons in the phantom: Woodcock tracking
+// ---------------------------------------------------------------------------------
+template <bool TAB_LDS>
+__global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
+{
+    // dynamic LDS: per wave two staging buffers of 12 x SBUF words + a fill count, then the
+    // tables when they are staged
+    extern __shared__ float lds[];
+    const int wave = threadIdx.x >> 6;
+    constexpr int SWORDS = 2 * (12 * SBUF + 1);
+    uint32_t *stage_base = (uint32_t *)lds + (size_t)wave * SWORDS;
+    float *tabs = lds + (WG / 64) * SWORDS;
+    const int ntab = P.nmat_ph * 3 * NB_PH;
+    if (TAB_LDS) {
+        for (int i = threadIdx.x; i < ntab; i += WG) tabs[i] = P.ph_tab[i];
+        for (int i = threadIdx.x; i < NB_PH; i += WG) tabs[ntab + i] = P.ph_maj[i];
+    }
+    if (threadIdx.x < 64) {
+        const int w = threadIdx.x >> 4, k = (threadIdx.x >> 3) & 1;
+        if ((threadIdx.x & 7) == 0 && w < WG / 64) ((uint32_t *)lds)[w * SWORDS + k * (12 * SBUF + 1) + 12 * SBUF] = 0;
+    }
+    __syncthreads();
+    const float *tab = TAB_LDS ? tabs : P.ph_tab;
+    const float *maj = TAB_LDS ? tabs + ntab : P.ph_maj;
+    Stages S;
+    S.e = stage_base;
+    S.g = stage_base + (12 * SBUF + 1);
+
+    const uint32_t n = min(P.cnt_in[QGP], P.cap[QGP]);
+    Win win{0, 0, 0};
+    bool active = false;
+    Part p;
+    Local L;
+    zero(L);
+    float mubar = 1.0f, mu0 = 0, mu1 = 0, mu2 = 0, mu3 = 0;
+    Node nd{0, 0.0f};
+    float e_cached = -1.0f;
+    unsigned long long lane_iters = 0, wave_iters = 0;
+    for (;;) {
+        stage_flush(P, S.e, QEP, SBUF / 2);
+        stage_flush(P, S.g, QGE, SBUF / 2);
+        const bool was = active;
+        refill(P, QGP, n, win, active, p);
+        const unsigned long long act = __ballot(active);
+        if (act == 0) break;
+        lane_iters += __popcll(act);
+        wave_iters += 64;
+        if (active && !was) ++L.items;
+        if (!active) continue;
+        if (p.E != e_cached) {
+            e_cached = p.E;
+            nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
+            mubar = lerp_tab(maj, nd);
+            mu0 = lerp_tab(tab + 0 * 3 * NB_PH, nd);
+            if (P.nmat_ph > 1) mu1 = lerp_tab(tab + 1 * 3 * NB_PH, nd);
+            if (P.nmat_ph > 2) mu2 = lerp_tab(tab + 2 * 3 * NB_PH, nd);
+            if (P.nmat_ph > 3) mu3 = lerp_tab(tab + 3 * 3 * NB_PH, nd);
+        }
+        const float4 r = rnd4(p, P);
+        // a flight longer than the box chord leaves the box either way (and an empty
+        // phantom, mubar = 0, must not produce an infinite step)
+        const float s = fminf(-__logf(r.x) / mubar, P.chord);
+        p.x = fmaf(s, p.u, p.x);
+        p.y = fmaf(s, p.v, p.y);
+        p.z = fmaf(s, p.w, p.z);
+        ++L.steps;
+        if (!in_phantom(P, p.x, p.y, p.z)) {
+            // leaves the box on a straight line: EPID or escape
+            place(P, 0, p, L, S);
+            active = false;
+            continue;
+        }
+        const int ix = min((int)(p.x * P.idx), P.nx - 1), iy = min((int)(p.y * P.idy), P.ny - 1),
+                  iz = min((int)(p.z * P.idz), P.nz - 1);
+        const uint32_t word = P.vox[((size_t)iz * P.ny + iy) * P.nx + ix];
+        const float rho = __uint_as_float(word & ~3u);
+        const int m = (int)(word & 3u);
+        const float mum = m == 0 ? mu0 : m == 1 ? mu1 : m == 2 ? mu2 : mu3;
+        if (r.y * mubar < rho * mum) {
+            active = photon_interact(P, 0, p, tab + m * 3 * NB_PH, nd, r.z, L, S);
+            if (!active) e_cached = -1.0f;
+        }
+    }
+    stage_flush(P, S.e, QEP, 1);
+    stage_flush(P, S.g, QGE, 1);
+    flush_stats(P, L, S_WOODCOCK, QGP, lane_iters, wave_iters);
+}
+
+template __global__ void k_photon_phantom<true>(Params);
+template __global__ void k_photon_phantom<false>(Params);
+
+// ---------------------------------------------------------------------------------
+// photons in the EPID: exact tracking across the slabs
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_photon_epid(Params P)
+{
+    extern __shared__ float lds[];
+    __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS];
+    const int ntab = P.nl * 3 * NB_PH;
+    const float *src = P.ph_tab + MAX_PMAT * 3 * NB_PH;
+    for (int i = threadIdx.x; i < ntab; i += WG) lds[i] = src[i];
+    if (threadIdx.x <= MAX_LAYERS) s_zl[threadIdx.x] = P.zl[threadIdx.x];
+    if (threadIdx.x < MAX_LAYERS) s_rho[threadIdx.x] = P.lrho[threadIdx.x];
+    __syncthreads();
+
+    const uint32_t n = min(P.cnt_in[QGE], P.cap[QGE]);
+    Win win{0, 0, 0};
+    bool active = false;
+    Part p;
+    Local L;
+    zero(L);
+    unsigned long long lane_iters = 0, wave_iters = 0;
+    for (;;) {
+        const bool was = active;
+        refill(P, QGE, n, win, active, p);
+        const unsigned long long act = __ballot(active);
+        if (act == 0) break;
+        lane_iters += __popcll(act);
+        wave_iters += 64;
+        if (active && !was) ++L.items;
+        if (!active) continue;
+        const int l = (int)((p.flags & F_LAYER_MASK) >> F_LAYER_SHIFT);
+        const float *tab = lds + l * 3 * NB_PH;
+        const Node nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
+        const float mu = s_rho[l] * lerp_tab(tab, nd);
+        // distance to the slab planes and to the lateral faces
+        float tz = INFINITY;
+        int dl = 0;
+        if (p.w > 0.0f) { tz = (s_zl[l + 1] - p.z) / p.w; dl = 1; }
+        else if (p.w < 0.0f) { tz = (s_zl[l] - p.z) / p.w; dl = -1; }
+        float tl = INFINITY;
+        if (p.u > 0.0f) tl = fminf(tl, (P.hx - p.x) / p.u);
+        else if (p.u < 0.0f) tl = fminf(tl, (-P.hx - p.x) / p.u);
+        if (p.v > 0.0f) tl = fminf(tl, (P.hy - p.y) / p.v);
+        else if (p.v < 0.0f) tl = fminf(tl, (-P.hy - p.y) / p.v);
+        tz = fmaxf(tz, 0.0f);
+        tl = fmaxf(tl, 0.0f);
+        const float4 r = rnd4(p, P);
+        const float s = -__logf(r.x) / mu;
+        ++L.steps;
+        if (s < fminf(tz, tl)) {
+            p.x = fmaf(s, p.u, p.x);
+            p.y = fmaf(s, p.v, p.y);
+            p.z = fmaf(s, p.w, p.z);
+            active = photon_interact(P, 1, p, tab, nd, r.y, L);
+            continue;
+        }
+        if (tl <= tz) {   // leaves through a lateral face
+            ledger(P, p.hist, (double)p.E);
+            active = false;
+            continue;
+        }
+        p.x = fmaf(tz, p.u, p.x);
+        p.y = fmaf(tz, p.v, p.y);
+        const int nlay = l + dl;
+        if (nlay < 0 || nlay >= P.nl) {
+            ledger(P, p.hist, (double)p.E);
+            active = false;
+            continue;
+        }
+        p.z = dl > 0 ? s_zl[l + 1] : s_zl[l];
+        p.flags = (p.flags & ~F_LAYER_MASK) | ((uint32_t)nlay << F_LAYER_SHIFT);
+    }
+    flush_stats(P, L, S_EPID_PH_STEPS, QGE, lane_iters, wave_iters);
+}
+
+// ---------------------------------------------------------------------------------
+// electrons and positrons: Class II condensed history, one step per loop iteration
+// ---------------------------------------------------------------------------------
+template <bool EPID>
+__global__ __launch_bounds__(WG) void k_electron(Params P)
+{
+    extern __shared__ float lds[];
+    __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS], s_smin[MAX_LAYERS], s_x0[MAX_PMAT + MAX_LAYERS];
+    const int nm = EPID ? P.nl : P.nmat_ph;
+    const float *src = P.el_tab + (EPID ? MAX_PMAT : 0) * 3 * NB_EL;
+    for (int i = threadIdx.x; i < nm * 3 * NB_EL; i += WG) lds[i] = src[i];
+    if (threadIdx.x <= MAX_LAYERS) s_zl[threadIdx.x] = P.zl[threadIdx.x];
+    if (threadIdx.x < MAX_LAYERS) {
+        s_rho[threadIdx.x] = P.lrho[threadIdx.x];
+        s_smin[threadIdx.x] = P.lsmin[threadIdx.x];
+    }
+    if (threadIdx.x < MAX_PMAT + MAX_LAYERS) s_x0[threadIdx.x] = P.el_x0[threadIdx.x];
+    __syncthreads();
+    const int kind = EPID ? QEE : QEP;
+    const int region = EPID ? 1 : 0;
+    const float ln09 = -0.105360515657826301f;   // ln 0.9
+
+    const uint32_t n = min(P.cnt_in[kind], P.cap[kind]);
+    Win win{0, 0, 0};
+    bool active = false;
+    Part p;
+    // positions advance in FP64: a 0.1 um nudge must move a particle across a face even
+    // 50 cm from the frame origin and at grazing incidence
+    double px = 0, py = 0, pz = 0;
+    Local L;
+    zero(L);
+    int nsteps = 0;
+    unsigned long long lane_iters = 0, wave_iters = 0;
+    for (;;) {
+        const bool was = active;
+        refill(P, kind, n, win, active, p);
+        const unsigned long long act = __ballot(active);
+        if (act == 0) break;
+        lane_iters += __popcll(act);
+        wave_iters += 64;
+        if (active && !was) {
+            ++L.items;
+            nsteps = 0;
+            px = p.x; py = p.y; pz = p.z;
+        }
+        if (!active) continue;
+        if (++nsteps > MAX_E_STEPS || !(p.E == p.E)) {
+            atomicOr(P.err, nsteps > MAX_E_STEPS ? ERR_STEPS : ERR_NAN);
+            ledger(P, p.hist, (double)p.E);
+            active = false;
+            continue;
+        }
+        ++L.steps;
+        // current cell and medium
+        float rho, smin;
+        double lo0, hi0, lo1, hi1, lo2, hi2;
+        int m, layer = -1;
+        if (!EPID) {
+            const int ix = min(max((int)(px / P.ddx), 0), P.nx - 1);
+            const int iy = min(max((int)(py / P.ddy), 0), P.ny - 1);
+            const int iz = min(max((int)(pz / P.ddz), 0), P.nz - 1);
+            const uint32_t word = P.vox[((size_t)iz * P.ny + iy) * P.nx + ix];
+            rho = __uint_as_float(word & ~3u);
+            m = (int)(word & 3u);
+            lo0 = ix * P.ddx; hi0 = lo0 + P.ddx;
+            lo1 = iy * P.ddy; hi1 = lo1 + P.ddy;
+            lo2 = iz * P.ddz; hi2 = lo2 + P.ddz;
+            smin = P.smin_ph;
+        } else {
+            int l = 0;
+#pragma unroll
+            for (int k = 1; k < MAX_LAYERS; ++k)
+                if (k < P.nl && pz >= (double)s_zl[k]) l = k;
+            layer = l;
+            m = l;
+            rho = s_rho[l];
+            lo0 = -P.hx; hi0 = P.hx; lo1 = -P.hy; hi1 = P.hy;
+            lo2 = s_zl[l]; hi2 = s_zl[l + 1];
+            smin = s_smin[l];
+        }
+        double dg = INFINITY;
+        if (p.u > 0.0f) dg = fmin(dg, (hi0 - px) / p.u); else if (p.u < 0.0f) dg = fmin(dg, (lo0 - px) / p.u);
+        if (p.v > 0.0f) dg = fmin(dg, (hi1 - py) / p.v); else if (p.v < 0.0f) dg = fmin(dg, (lo1 - py) / p.v);
+        if (p.w > 0.0f) dg = fmin(dg, (hi2 - pz) / p.w); else if (p.w < 0.0f) dg = fmin(dg, (lo2 - pz) / p.w);
+        const float sg = fmaxf((float)fmax(dg, 0.0) + NUDGE, smin);
+        float T = p.E;
+        if (!(rho > 0.0f)) {
+            px += (double)sg * p.u;
+            py += (double)sg * p.v;
+            pz += (double)sg * p.w;
+        } else {
+            const float *tab = lds + m * 3 * NB_EL;
+            const float lnT = __logf(T);
+            const Node n0 = node_of(lnT, P.el_lnT0, P.el_idl, NB_EL);
+            const float R0 = lerp_tab(tab, n0);
+            const float sh = lerp_tab(tab + NB_EL, n0);
+            const Node n9 = node_of(lnT + ln09, P.el_lnT0, P.el_idl, NB_EL);
+            const float R9 = lerp_tab(tab, n9);
+            const float4 r = rnd4(p, P);
+            const float irho = 1.0f / rho;
+            const float s_hard = sh > 0.0f ? -__logf(r.x) / (rho * sh) : INFINITY;
+            const float s_de = (R0 - R9) * irho;
+            const float s_pix = (EPID && layer == P.scoring) ? P.s_pix : INFINITY;
+            const float s = fminf(fminf(s_hard, s_de), fminf(sg, s_pix));
+            const bool hard = s_hard <= fminf(s_de, fminf(sg, s_pix));
+            float T1;
+            if (s == s_de) {
+                T1 = DE_FRAC * T;
+            } else {
+                // invert the range table: find j with R[j] <= Rt < R[j+1] between the 0.9 T0 node and T0's
+                const float Rt = R0 - rho * s;
+                int lo = n9.i, hi = n0.i + 1;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (tab[mid] <= Rt) lo = mid; else hi = mid;
+                }
+                const float d = tab[lo + 1] - tab[lo];
+                const float f = d > 0.0f ? fminf(fmaxf((Rt - tab[lo]) / d, 0.0f), 1.0f) : 0.0f;
+                T1 = fminf(__expf(P.el_lnT0 + ((float)lo + f) / P.el_idl), T);
+            }
+            // hinge point: the step's continuous loss is deposited there
+            const double a = (double)(r.y * s);
+            px += a * p.u;
+            py += a * p.v;
+            pz += a * p.w;
+            const float dep = T - T1;
+            if (P.diag) ledger(P, p.hist, (double)T - (double)T1);
+            if (EPID && layer == P.scoring) {
+                tally(P, p.flags, (float)px, (float)py, dep);
+                ++L.tally;
+            }
+            if (!(P.mask & 16u)) {
+                const float th = highland(T, rho * s, s_x0[(EPID ? MAX_PMAT : 0) + m]) * sqrtf(-2.0f * __logf(r.z));
+                float sth, cth, sp, cp;
+                __sincosf(th, &sth, &cth);
+                __sincosf(TWO_PI_F * r.w, &sp, &cp);
+                rotate(p.u, p.v, p.w, cth, sth, cp, sp);
+            }
+            const double b = (double)s - a;
+            px += b * p.u;
+            py += b * p.v;
+            pz += b * p.w;
+            T = T1;
+            p.E = T;
+            if (hard) {
+                p.x = (float)px; p.y = (float)py; p.z = (float)pz;
+                const Node n1 = node_of(__logf(T), P.el_lnT0, P.el_idl, NB_EL);
+                const float fm = lerp_tab(tab + 2 * NB_EL, n1);
+                const float4 r2 = rnd4(p, P);
+                if (r2.x < fm && T > 2.0f * (float)WCUT) {
+                    ++L.moller;
+                    float phu;
+                    const float W = moller_sample(P, p, T, phu);
+                    const float Tp = T - W;
+                    const float tt = T + 2.0f * MEC2F;
+                    const float cd = fminf(1.0f, sqrtf(W * tt / (T * (W + 2.0f * MEC2F))));
+                    const float cq = fminf(1.0f, sqrtf(Tp * tt / (T * (Tp + 2.0f * MEC2F))));
+                    float sp, cp;
+                    __sincosf(TWO_PI_F * phu, &sp, &cp);
+                    float du = p.u, dv = p.v, dw = p.w;
+                    rotate(du, dv, dw, cd, sqrtf(fmaxf(0.0f, 1.0f - cd * cd)), cp, sp);
+                    rotate(p.u, p.v, p.w, cq, sqrtf(fmaxf(0.0f, 1.0f - cq * cq)), -cp, -sp);
+                    if (P.diag) ledger(P, p.hist, (double)T - (double)Tp - (double)W);
+                    T = Tp;
+                    p.E = T;
+                    emit_electron(P, region, p, W, 1u, du, dv, dw, L);
+                } else {
+                    ++L.brems;
+                    const float k = (float)KCUT * __expf(r2.y * __logf(T * (float)(1.0 / KCUT)));
+                    const float Tn = T - k;
+                    if (P.diag) ledger(P, p.hist, (double)T - (double)Tn - (double)k);
+                    T = Tn;
+                    p.E = T;
+                    emit_photon(P, region, p, k, p.u, p.v, p.w, L);
+                }
+            }
+        }
+        p.x = (float)px; p.y = (float)py; p.z = (float)pz;
+        if (T < P.ecut) {
+            deposit_point(P, region, p, T, L);
+            if ((p.flags & F_TYPE) == 2u) annihilate(P, region, p, L);
+            active = false;
+            continue;
+        }
+        // where is the end point
+        if (!EPID) {
+            const bool inside = px >= 0.0 && px < (double)P.Lx && py >= 0.0 && py < (double)P.Ly && pz >= 0.0 &&
+                                pz < (double)P.Lz;
+            if (!inside) {
+                const int r = vacuum_phantom_frame(P, p);
+                if (r == 0) {
+                    px = p.x; py = p.y; pz = p.z;   // re-entered through a face
+                } else {
+                    if (r == 1) qappend(P, QEE, true, p);
+                    else ledger(P, p.hist, (double)p.E);
+                    active = false;
+                }
+            }
+        } else {
+            const bool inside = px >= (double)-P.hx && px < (double)P.hx && py >= (double)-P.hy && py < (double)P.hy &&
+                                pz >= 0.0 && pz < (double)P.zback;
+            if (!inside) {
+                ledger(P, p.hist, (double)p.E);
+                active = false;
+            }
+        }
+    }
+    flush_stats(P, L, EPID ? S_ESTEP_E : S_ESTEP_P, kind, lane_iters, wave_iters);
+}
+
+template __global__ void k_electron<false>(Params);
+template __global__ void k_electron<true>(Params);
+
+// ---------------------------------------------------------------------------------
+// tally folding, image, sigma-bar, diagnostics
+// ---------------------------------------------------------------------------------
+struct FoldArgs {
+    double nb[MAX_SLOTS];   // histories of each batch to fold
+    int slot[MAX_SLOTS];    // its image slot; batches are listed (and added) in batch order
+    int n;
+};
+
+__global__ void k_fold(Params P, FoldArgs A)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.npix; i += gridDim.x * blockDim.x) {
+        double s = P.sum[i], s2 = P.sum2[i];
+        for (int j = 0; j < A.n; ++j) {
+            const size_t k = (size_t)A.slot[j] * P.npix + i;
+            double v;
+            if (P.tally_mode == 1) {
+                const unsigned long long q = ((unsigned long long *)P.img)[k];
+                if (q >= (1ull << 62)) atomicOr(P.err, ERR_FIXED);
+                v = (double)q * (1.0 / 4294967296.0);
+                ((unsigned long long *)P.img)[k] = 0;
+            } else {
+                v = ((double *)P.img)[k];
+                ((double *)P.img)[k] = 0.0;
+            }
+            s += v;
+            s2 += v * v / A.nb[j];
+        }
+        P.sum[i] = s;
+        P.sum2[i] = s2;
+    }
+}
+
+// Kahan mode: reduce deposit records into the slot images.  Records are binned by their
+// image index with a counting sort, then one thread per image element adds its records in
+// FP32 with Kahan compensation and writes the total (no atomics on the image).
+__global__ void k_rec_count(const uint32_t *pix, uint32_t n, uint32_t *count)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        atomicAdd(&count[pix[i]], 1u);
+}
+
+// exclusive scan in place, three phases: block sums, scan of block sums, add
+__global__ void k_scan_blocks(uint32_t *a, uint32_t n, uint32_t *bsum)
+{
+    __shared__ uint32_t s[1024];
+    const uint32_t i = blockIdx.x * 1024 + threadIdx.x;
+    const uint32_t v = i < n ? a[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) a[i] = s[threadIdx.x] - v;
+    if (threadIdx.x == 1023) bsum[blockIdx.x] = s[1023];
+}
+
+__global__ void k_scan_top(uint32_t *bsum, uint32_t nb)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t b = 0; b < nb; ++b) { const uint32_t t = bsum[b]; bsum[b] = acc; acc += t; }
+    }
+}
+
+__global__ void k_scan_add(uint32_t *a, uint32_t n, const uint32_t *bsum)
+{
+    const uint32_t i = blockIdx.x * 1024 + threadIdx.x;
+    if (i < n) a[i] += bsum[blockIdx.x];
+}
+
+__global__ void k_rec_scatter(const uint32_t *pix, const float *e, uint32_t n, uint32_t *cursor, float *sorted)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t k = atomicAdd(&cursor[pix[i]], 1u);
+        sorted[k] = e[i];
+    }
+}
+
+__global__ void k_rec_kahan(const uint32_t *start, const uint32_t *end, const float *sorted, uint32_t nimg,
+                            double *img)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nimg; i += gridDim.x * blockDim.x) {
+        float s = 0.0f, c = 0.0f;
+        for (uint32_t k = start[i]; k < end[i]; ++k) {
+            const float y = sorted[k] - c;
+            const float t = s + y;
+            c = (t - s) - y;
+            s = t;
+        }
+        img[i] += (double)s - (double)c;
+    }
+}
+
+__global__ void k_image(Params P, double n, double nbatch, double *mean, double *var)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P.npix; i += gridDim.x * blockDim.x) {
+        const double s = P.sum[i], s2 = P.sum2[i];
+        mean[i] = s / n;
+        const double v = (nbatch > 1.0) ? (s2 - s * s / n) / (n * (nbatch - 1.0)) : 0.0;
+        var[i] = v > 0.0 ? v : 0.0;
+    }
+}
+
+// one block: max of the mean, then the mean of sigma/D over pixels above threshold
+__global__ void k_sigma_bar(Params P, double n, double nbatch, double thr, double *out)
+{
+    __shared__ double red[1024];
+    __shared__ double cnt[1024];
+    double mx = 0.0;
+    for (uint32_t i = threadIdx.x; i < P.npix; i += blockDim.x) mx = fmax(mx, P.sum[i]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const double cut = thr * red[0];
+    __syncthreads();
+    double acc = 0.0, c = 0.0;
+    for (uint32_t i = threadIdx.x; i < P.npix; i += blockDim.x) {
+        const double s = P.sum[i];
+        if (s > 0.0 && s >= cut) {
+            const double m = s / n;
+            double v = (nbatch > 1.0) ? (P.sum2[i] - s * s / n) / (n * (nbatch - 1.0)) : 0.0;
+            v = v > 0.0 ? v : 0.0;
+            acc += sqrt(v) / m;
+            c += 1.0;
+        }
+    }
+    red[threadIdx.x] = acc;
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) {
+            red[threadIdx.x] += red[threadIdx.x + o];
+            cnt[threadIdx.x] += cnt[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = cnt[0] > 0 ? red[0] / cnt[0] : INFINITY;
+}
+
+// per-history ledger check: residual = |E_in - sum of ledger| / E_in
+__global__ void k_diag_check(Params P, uint32_t nh, unsigned long long *maxbits, double *sums)
+{
+    double ein = 0.0, led = 0.0, mx = 0.0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += gridDim.x * blockDim.x) {
+        const double a = P.ein[i], b = P.led[i];
+        ein += a;
+        led += b;
+        if (a > 0.0) mx = fmax(mx, fabs(a - b) / a);
+        P.led[i] = 0.0;
+    }
+    atomicMax(maxbits, (unsigned long long)__double_as_longlong(mx));
+    unsafeAtomicAdd(&sums[0], ein);
+    unsafeAtomicAdd(&sums[1], led);
+}
+
+__global__ void k_zero_u32(uint32_t *a, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = 0;
+}
+__global__ void k_zero_u64(unsigned long long *a, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = 0;
+}
+
+// ---------------------------------------------------------------------------------
+// building-block probes
+// ---------------------------------------------------------------------------------
+__global__ void k_dbg_philox(Params P, const uint32_t *ctr, uint32_t *out, unsigned long long n)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 r = philox10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], P.key0, P.key1);
+    out[4 * i] = r.x; out[4 * i + 1] = r.y; out[4 * i + 2] = r.z; out[4 * i + 3] = r.w;
+}
+
+__global__ void k_dbg_sample(Params P, int kind, float p0, float p1, float p2, float *out, unsigned long long n)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Part p;
+    p.hist = (uint32_t)i; p.plo = 0x5A5Au; p.phi = (uint32_t)kind; p.draw = 0; p.flags = 0;
+    float phu;
+    if (kind == 0) {
+        float t;
+        out[i] = kn_sample(P, p, p0, t, phu);
+    } else if (kind == 1) {
+        out[i] = moller_sample(P, p, p0, phu);
+    } else if (kind == 2) {
+        const float4 r = rnd4(p, P);
+        out[i] = (float)KCUT * __expf(r.y * __logf(p0 * (float)(1.0 / KCUT)));
+    } else if (kind == 3) {
+        const float4 r = rnd4(p, P);
+        out[i] = highland(p0, p1, p2) * sqrtf(-2.0f * __logf(r.z));
+    }
+}
+
+__global__ void k_dbg_table(Params P, int kind, int index, const float *E, float *out, unsigned long long n)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (kind == 0) {
+        const Node nd = node_of(__logf(E[i]), P.ph_lnE0, P.ph_idl, NB_PH);
+        out[i] = lerp_tab(P.ph_tab + index * 3 * NB_PH, nd);
+    } else {
+        const Node nd = node_of(__logf(E[i]), P.el_lnT0, P.el_idl, NB_EL);
+        out[i] = lerp_tab(P.el_tab + index * 3 * NB_EL + (kind == 2 ? NB_EL : 0), nd);
+    }
+}
+
+// source probe: the source kernel's sampling without transport
+__global__ void k_dbg_source(Params P, unsigned long long h0, float *out, unsigned long long n)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long h = h0 + i;
+    Part p;
+    p.hist = (uint32_t)h; p.plo = 0; p.phi = 0; p.draw = 0;
+    float gx, gy, gz;
+    const float4 r = rnd4(p, P);
+    int b = min((int)(r.x * (float)P.nbins), P.nbins - 1);
+    if (r.y >= P.sp_prob[b]) b = P.sp_alias[b];
+    p.E = fmaf(r.z, P.sp_hi[b] - P.sp_lo[b], P.sp_lo[b]);
+    int s = 0;
+    if (P.n_seg > 1) {
+        int lo = 0, hi = P.n_seg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (h < P.seg_end[mid]) hi = mid; else lo = mid + 1;
+        }
+        s = lo;
+    }
+    const float4 r2 = rnd4(p, P);
+    const int base = s * P.n_pairs;
+    int k = min((int)(r2.x * (float)P.n_pairs), P.n_pairs - 1);
+    if (r2.y >= P.ap_prob[base + k]) k = P.ap_alias[base + k];
+    const float a = P.ap_a[base + k], bb = P.ap_b[base + k];
+    const float x = fmaf(r2.z, bb - a, a);
+    const float y = fmaf((float)k + r2.w, P.leaf_w, P.y0);
+    if (P.beam_kind == 0) {
+        gx = x; gy = y; gz = P.src[2];
+        p.u = 0.0f; p.v = 0.0f; p.w = 1.0f;
+    } else {
+        const float dx = x - P.src[0], dy = y - P.src[1], dz = P.iso_z - P.src[2];
+        const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+        gx = P.src[0]; gy = P.src[1]; gz = P.src[2];
+        p.u = dx * inv; p.v = dy * inv; p.w = dz * inv;
+    }
+    float *o = out + 8 * i;
+    o[0] = gx; o[1] = gy; o[2] = gz; o[3] = p.u; o[4] = p.v; o[5] = p.w; o[6] = p.E; o[7] = 0.0f;
+}
+
+// ---------------------------------------------------------------------------------
+// launchers (host side of this translation unit)
+// ---------------------------------------------------------------------------------
+static inline unsigned grid_for(unsigned long long n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+// the Woodcock kernel touches its tables only when a photon's energy changes, so they are
+// read through the caches; LDS holds the staged appends instead (0 = tables in L1/L2)
+#ifndef PH_TAB_LDS
+#define PH_TAB_LDS 0
+#endif
+
+hipError_t launch_source(const Params &P, hipStream_t s)
+{
+    const unsigned long long n = P.h1 - P.h0;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_source, dim3(grid_for(n, WG)), dim3(WG), 0, s, P);
+    return hipGetLastError();
+}
+
+size_t lds_bytes(int kind, const Params &P)
+{
+    switch (kind) {
+    case QGP: return (size_t)(WG / 64) * 2 * (12 * SBUF + 1) * 4 + (PH_TAB_LDS ? (size_t)(P.nmat_ph * 3 + 1) * NB_PH * 4 : 0);
+    case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float);
+    case QEP: return (size_t)P.nmat_ph * 3 * NB_EL * sizeof(float);
+    default: return (size_t)P.nl * 3 * NB_EL * sizeof(float);
+    }
+}
+
+hipError_t launch_transport(int kind, const Params &P, unsigned blocks, hipStream_t s)
+{
+    const size_t lds = lds_bytes(kind, P);
+    switch (kind) {
+    case QGP: hipLaunchKernelGGL(k_photon_phantom<PH_TAB_LDS>, dim3(blocks), dim3(WG), lds, s, P); break;
+    case QGE: hipLaunchKernelGGL(k_photon_epid, dim3(blocks), dim3(WG), lds, s, P); break;
+    case QEP: hipLaunchKernelGGL(k_electron<false>, dim3(blocks), dim3(WG), lds, s, P); break;
+    default: hipLaunchKernelGGL(k_electron<true>, dim3(blocks), dim3(WG), lds, s, P); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t set_lds_limits()
+{
+    // allow the dynamic LDS sizes above the default 64 KiB cap
+    hipError_t e = hipSuccess;
+    const int big = 160 * 1024;
+    e = hipFuncSetAttribute((const void *)k_photon_phantom<PH_TAB_LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_photon_epid, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_electron<false>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_electron<true>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+}
+
+hipError_t launch_fold(const Params &P, const int *slots, const double *nb, int n, hipStream_t s)
+{
+    FoldArgs A;
+    for (int i = 0; i < MAX_SLOTS; ++i) {
+        A.nb[i] = i < n ? nb[i] : 1.0;
+        A.slot[i] = i < n ? slots[i] : 0;
+    }
+    A.n = n;
+    hipLaunchKernelGGL(k_fold, dim3(min(grid_for(P.npix, 256), 4096u)), dim3(256), 0, s, P, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_kahan_reduce(const Params &P, uint32_t nrec, uint32_t nimg, uint32_t *count, uint32_t *cursor,
+                               uint32_t *bsum, float *sorted, hipStream_t s)
+{
+    if (nrec == 0) return hipSuccess;
+    const unsigned g = min(grid_for(nimg, 256), 8192u);
+    hipLaunchKernelGGL(k_zero_u32, dim3(g), dim3(256), 0, s, count, (size_t)nimg);
+    hipLaunchKernelGGL(k_rec_count, dim3(min(grid_for(nrec, 256), 8192u)), dim3(256), 0, s, P.rec_pix, nrec, count);
+    const unsigned nb = grid_for(nimg, 1024);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, nimg, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(64), 0, s, bsum, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, s, count, nimg, bsum);
+    // count now holds segment starts; cursor (a copy) advances to the segment ends
+    const hipError_t e = hipMemcpyAsync(cursor, count, (size_t)nimg * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rec_scatter, dim3(min(grid_for(nrec, 256), 8192u)), dim3(256), 0, s, P.rec_pix, P.rec_e,
+                       nrec, cursor, sorted);
+    hipLaunchKernelGGL(k_rec_kahan, dim3(g), dim3(256), 0, s, count, cursor, sorted, nimg, (double *)P.img);
+    return hipGetLastError();
+}
+
+hipError_t launch_image(const Params &P, double n, double nb, double *mean, double *var, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_image, dim3(min(grid_for(P.npix, 256), 4096u)), dim3(256), 0, s, P, n, nb, mean, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_sigma_bar(const Params &P, double n, double nb, double thr, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sigma_bar, dim3(1), dim3(1024), 0, s, P, n, nb, thr, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_check(const Params &P, uint32_t nh, unsigned long long *maxbits, double *sums, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_diag_check, dim3(min(grid_for(nh, 256), 2048u)), dim3(256), 0, s, P, nh, maxbits, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 8 == 0 && ((uintptr_t)p % 8) == 0) {
+        const size_t n = bytes / 8;
+        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)min((n + 255) / 256, (size_t)8192)), dim3(256), 0, s,
+                           (unsigned long long *)p, n);
+    } else {
+        const size_t n = (bytes + 3) / 4;
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)min((n + 255) / 256, (size_t)8192)), dim3(256), 0, s,
+                           (uint32_t *)p, n);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dbg_philox(const Params &P, const uint32_t *ctr, uint32_t *out, unsigned long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dbg_philox, dim3(grid_for(n, 256)), dim3(256), 0, s, P, ctr, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dbg_sample(const Params &P, int kind, float p0, float p1, float p2, float *out,
+                             unsigned long long n, hipStream_t s)
+{
+    if (kind == 4) {
+        hipLaunchKernelGGL(k_dbg_source, dim3(grid_for(n, 256)), dim3(256), 0, s, P, (unsigned long long)p0, out, n);
+    } else {
+        hipLaunchKernelGGL(k_dbg_sample, dim3(grid_for(n, 256)), dim3(256), 0, s, P, kind, p0, p1, p2, out, n);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dbg_table(const Params &P, int kind, int index, const float *E, float *out, unsigned long long n,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dbg_table, dim3(grid_for(n, 256)), dim3(256), 0, s, P, kind, index, E, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace epidmc

@@ -1,0 +1,204 @@
+"""GPU tests of the engine's building blocks through the C ABI: the device Philox
+stream, samplers, cross-section tables and source, each against the oracle or
+against analytic densities."""
+import ctypes as ct
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+from paper_2510_24154_amd import synth
+
+pytestmark = pytest.mark.gpu
+MEC2 = 0.51099895
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_24154_amd as E
+    return E
+
+
+def oracle_philox(orc, ctr, key):
+    out = np.zeros((len(ctr), 4), np.uint32)
+    k = np.array(key, np.uint32)
+    for i, c in enumerate(ctr):
+        c = np.ascontiguousarray(c, np.uint32)
+        orc.lib().orc_philox4x32_10(c.ctypes.data, k.ctypes.data, out[i].ctypes.data)
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 0xFFFFFFFFFFFFFFFF, 0x299F31D0A4093822, 12345])
+def test_device_philox_matches_oracle(E, orc, seed):
+    eng = E.Engine(0, seed=seed)
+    rng = np.random.default_rng(seed & 0xFFFF)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = [0, 0, 0, 0]
+    ctr[1] = [0xFFFFFFFF] * 4
+    ctr[2] = [0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344]
+    dev = eng.debug_philox(ctr)
+    ref = oracle_philox(orc, ctr, [seed & 0xFFFFFFFF, seed >> 32])
+    assert np.array_equal(dev, ref)
+
+
+def kn_dens(E, c):
+    P = 1.0 / (1.0 + E / MEC2 * (1.0 - c))
+    return P * P * (P + 1.0 / P - (1.0 - c * c))
+
+
+def chi2_p(obs, exp):
+    keep = exp > 5
+    chi2 = float(np.sum((obs[keep] - exp[keep]) ** 2 / exp[keep]))
+    return stats.chi2.sf(chi2, int(keep.sum()) - 1)
+
+
+@pytest.mark.parametrize("En", [0.03, 0.3, 2.0, 6.0])
+def test_device_kn_sampler(E, En):
+    eng = E.Engine(0, seed=7)
+    n = 1_000_000
+    eps = eng.debug_sample(0, n, En).astype(np.float64)
+    k = En / MEC2
+    assert eps.min() >= 1 / (1 + 2 * k) * (1 - 1e-6) and eps.max() <= 1.0
+    c = 1.0 - (1.0 / eps - 1.0) / k
+    edges = np.linspace(-1, 1, 51)
+    obs, _ = np.histogram(c, edges)
+    tot = integrate.quad(lambda x: kn_dens(En, x), -1, 1, points=[0.9, 0.99], epsrel=1e-12)[0]
+    exp = np.array([integrate.quad(lambda x: kn_dens(En, x), a, b, epsrel=1e-12)[0]
+                    for a, b in zip(edges[:-1], edges[1:])]) / tot * n
+    assert chi2_p(obs, exp) > 1e-4
+
+
+def moller_dens(T, W):
+    g = T / MEC2 + 1
+    Tp = T - W
+    return 1 / W ** 2 + 1 / Tp ** 2 + ((g - 1) / g) ** 2 / T ** 2 - (2 * g - 1) / g ** 2 / (W * Tp)
+
+
+@pytest.mark.parametrize("T", [0.5, 1.5, 5.0])
+def test_device_moller_sampler(E, T):
+    eng = E.Engine(0, seed=8)
+    n = 500_000
+    W = eng.debug_sample(1, n, T).astype(np.float64)
+    assert W.min() >= 0.2 * (1 - 1e-5) and W.max() <= T / 2 * (1 + 1e-5)
+    edges = np.linspace(0.2, T / 2, 41)
+    obs, _ = np.histogram(np.clip(W, 0.2, T / 2), edges)
+    tot = integrate.quad(lambda w: moller_dens(T, w), 0.2, T / 2, epsrel=1e-12)[0]
+    exp = np.array([integrate.quad(lambda w: moller_dens(T, w), a, b, epsrel=1e-12)[0]
+                    for a, b in zip(edges[:-1], edges[1:])]) / tot * n
+    assert chi2_p(obs, exp) > 1e-4
+
+
+def test_device_brems_sampler(E):
+    eng = E.Engine(0, seed=9)
+    T, n = 3.0, 500_000
+    k = eng.debug_sample(2, n, T).astype(np.float64)
+    assert k.min() >= 0.01 * (1 - 1e-5) and k.max() <= T * (1 + 1e-5)
+    # ln(k/kc) / ln(T/kc) is uniform for a 1/k spectrum
+    u = np.log(k / 0.01) / math.log(T / 0.01)
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("T,x", [(0.5, 0.05), (2.0, 0.2), (5.0, 0.01)])
+def test_device_msc_rayleigh(E, orc, T, x):
+    """Deflection angles follow a Rayleigh law whose width is the oracle's Highland theta0."""
+    eng = E.Engine(0, seed=10)
+    X0 = orc.lib().orc_x0(ct.byref(orc.material(synth.WATER)))
+    th = eng.debug_sample(3, 200_000, T, x, X0).astype(np.float64)
+    t0 = orc.lib().orc_highland(T, x, X0)
+    assert stats.kstest(th, "rayleigh", args=(0, t0)).pvalue > 1e-3
+
+
+def _bound_engine(E, cfg, **kw):
+    eng = E.Engine(0, seed=1).configure(cfg, **kw)
+    eng.bind()
+    return eng
+
+
+def test_device_photon_tables_match_oracle(E, orc):
+    """mu/rho interpolated on the device against the oracle's formulas: < 1e-4 relative
+    over the table range, for every phantom and EPID material of the coupled workload."""
+    cfg = synth.coupled_hetero_small()
+    eng = _bound_engine(E, cfg, batches=16, max_chunk=1 << 12)
+    Es = np.exp(np.random.default_rng(3).uniform(math.log(0.0101), math.log(6.0), 2000)).astype(np.float32)
+    # phantom slots are the distinct phantom materials in increasing index order
+    present = sorted(set(orc.map_hu(cfg["phantom"]["hu"], cfg["phantom"]["curve"], cfg["phantom"]["ranges"])[0]))
+    slots = [(i, cfg["materials"][m]) for i, m in enumerate(present)]
+    slots += [(4 + l, cfg["materials"][L["mat"]]) for l, L in enumerate(cfg["epid"]["layers"])]
+    out = np.zeros(4)
+    for slot, m in slots:
+        dev = eng.debug_table(0, slot, Es).astype(np.float64)
+        ref = []
+        for e in Es.astype(np.float64):
+            orc.lib().orc_photon_mu(ct.byref(orc.material(m)), e, out.ctypes.data)
+            ref.append(out[0])
+        np.testing.assert_allclose(dev, ref, rtol=1e-4)
+
+
+def test_device_electron_tables_match_oracle(E, orc):
+    """Range differences and hard cross sections from the device tables against the
+    oracle's quadrature and closed forms."""
+    cfg = synth.coupled_hetero_small()
+    eng = _bound_engine(E, cfg, batches=16, max_chunk=1 << 12)
+    L = orc.lib()
+    rng = np.random.default_rng(4)
+    T0 = np.exp(rng.uniform(math.log(0.2), math.log(5.5), 400)).astype(np.float32)
+    T1 = (T0 * 0.9).astype(np.float32)
+    for slot, m in [(4, synth.COPPER), (6, synth.GOS)]:
+        mm = orc.material(m)
+        dR = eng.debug_table(1, slot, T0).astype(np.float64) - eng.debug_table(1, slot, T1).astype(np.float64)
+        ref = np.array([L.orc_range_diff(ct.byref(mm), float(a), float(b), 0.2, 0.01) for a, b in zip(T1, T0)])
+        np.testing.assert_allclose(dR, ref, rtol=2e-3)
+        sh = eng.debug_table(2, slot, T0).astype(np.float64)
+        refh = np.array([L.orc_sigma_moller(ct.byref(mm), float(t), 0.2) + L.orc_sigma_brems(ct.byref(mm), float(t), 0.01)
+                         for t in T0])
+        np.testing.assert_allclose(sh, refh, rtol=2e-3, atol=1e-6)
+
+
+def test_device_source_matches_oracle_distribution(E, orc):
+    """Spectrum, aperture and direction sampling: the device source and the oracle's source
+    describe the same distribution (two-sample KS on energy and iso-plane position)."""
+    cfg = synth.imrt_field(total=300_000_000)
+    eng = _bound_engine(E, cfg, batches=16, max_chunk=1 << 12)
+    ap = cfg["source"]["aperture"]
+    first = int(ap["counts"][:5].sum())
+    n = 100_000
+    dev = eng.debug_sample(4, n, first).astype(np.float64)
+    ref = orc.source(cfg, np.arange(first, first + 20_000), seed=1001)
+    assert stats.ks_2samp(dev[:, 6], ref[:, 6]).pvalue > 1e-3
+    for d in (dev, ref):
+        t = 100.0 / d[:, 5]
+        d[:, 0], d[:, 1] = d[:, 3] * t, d[:, 4] * t
+    assert stats.ks_2samp(dev[:, 0], ref[:, 0]).pvalue > 1e-3
+    assert stats.ks_2samp(dev[:, 1], ref[:, 1]).pvalue > 1e-3
+    k = np.floor((dev[:, 1] - ap["y0"]) / ap["leaf_w"]).astype(int)
+    assert np.all((dev[:, 0] >= ap["a"][5][k] - 1e-4) & (dev[:, 0] <= ap["b"][5][k] + 1e-4))
+
+
+def test_abi_validation_errors(E):
+    eng = E.Engine(0, seed=1)
+    with pytest.raises(E.EpidmcError) as e:
+        eng.run(1000)
+    assert e.value.code == -4          # not ready
+    with pytest.raises(E.EpidmcError) as e:
+        eng.set_physics(1, 0, 0.01, 0.2)
+    assert e.value.code == -1          # no photon process
+    with pytest.raises(E.EpidmcError) as e:
+        eng.set_phantom_direct(np.zeros(8, np.uint8), np.full(8, np.nan, np.float32), (2, 2, 2), (1, 1, 1), (0, 0, 0))
+    assert e.value.code in (-1, -3)
+    eng.set_materials([synth.WATER])
+    with pytest.raises(E.EpidmcError) as e:
+        eng.set_phantom_direct(np.zeros(8, np.uint8), np.ones(8, np.float32), (2, 2, 2), (0, 1, 1), (0, 0, 0))
+    assert e.value.code == -1          # zero spacing
+    with pytest.raises(E.EpidmcError) as e:
+        eng.set_segments(np.array([[1.0, 2.0]]), np.array([[0.0, 3.0]]), 0.5, 0.0)
+    assert e.value.code == -1          # a > b
+    with pytest.raises(E.EpidmcError) as e:
+        eng.set_source_spectrum([1.0, 0.5], [1.0], {"kind": 1, "src": (0, 0, 0), "iso_z": 100})
+    assert e.value.code == -1          # decreasing edges
+    with pytest.raises(E.EpidmcError) as e:
+        eng.set_tally(7, 64, 1 << 20)
+    assert e.value.code == -1

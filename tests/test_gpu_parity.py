@@ -1,0 +1,233 @@
+"""GPU parity tests through the C ABI: the HIP transport against the CPU oracle on
+the same seeded workloads (different random streams), and against closed forms.
+
+Parity is statistical (Monte Carlo): per-pixel standard scores of the difference,
+judged as a population (z-gate), plus exact closed forms where they exist, the
+per-history energy ledger, and bit-exact invariants of the fixed-point tally."""
+import copy
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2510_24154_amd import synth
+from tests._stats import gamma_pass, rebin, sigma_bar, z_gate
+
+pytestmark = pytest.mark.gpu
+THREADS = max(1, min(16, os.cpu_count() or 1))
+_ORACLE_CACHE = {}
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_24154_amd as E
+    return E
+
+
+def oracle_image(orc, key, cfg, n, seed=1001):
+    if key not in _ORACLE_CACHE:
+        print(f"[oracle] {key}: {n} histories on {THREADS} threads", flush=True)
+        _ORACLE_CACHE[key] = orc.run(cfg, n, seed=seed, threads=THREADS)
+    return _ORACLE_CACHE[key]
+
+
+def gpu_image(E, cfg, n, seed=1, **kw):
+    kw.setdefault("batches", 64)
+    kw.setdefault("max_chunk", 1 << 22)
+    eng = E.Engine(0, seed=seed).configure(cfg, **kw)
+    eng.bind()
+    eng.run(n)
+    m, v = eng.image()
+    return m.cpu().numpy(), v.cpu().numpy(), eng
+
+
+def mu(orc, m, En, mask):
+    import ctypes as ct
+    out = np.zeros(4)
+    orc.lib().orc_photon_mu(ct.byref(orc.material(m)), En, out.ctypes.data)
+    return sum(out[1 + i] for i in range(3) if mask >> i & 1)
+
+
+def test_transmission_water_box(E, orc):
+    """Woodcock tracking in the phantom: unscattered primaries behind 20 cm of water
+    are exp(-20 mu) (binomial z)."""
+    n = 4_000_000
+    _, _, eng = gpu_image(E, synth.kerma_water(), n)
+    c = eng.counters()
+    p = math.exp(-20.0 * mu(orc, synth.WATER, 2.0, 0b011))
+    z = (c["unscattered_at_epid"] - n * p) / math.sqrt(n * p * (1 - p))
+    assert abs(z) < 4, z
+
+
+def test_transmission_heterogeneous_slabs(E, orc):
+    """Delta tracking through bone, lung, air and water slabs against exp(-sum mu rho t):
+    exercises the majorant across materials and densities."""
+    cfg = synth.coupled_hetero_small()
+    cfg["physics"]["coupled"] = 0
+    cfg["source"] = synth.kerma_water()["source"]
+    cfg["source"]["edges"] = np.array([0.6, 0.6])
+    slabs = [(2, 1.0, 10), (3, 1.6, 7), (1, 0.3, 20), (3, 1.85, 3), (0, 0.0012, 5), (2, 1.0, 15)]
+    nz = sum(s[2] for s in slabs)
+    mats = np.concatenate([np.full(s[2], s[0], np.uint8) for s in slabs])
+    rhos = np.concatenate([np.full(s[2], s[1], np.float32) for s in slabs])
+    cfg["phantom"] = {"kind": "direct", "shape": (4, 4, nz), "spacing": (5.0, 5.0, 0.2), "origin": (-10.0, -10.0, 0.0),
+                      "mat": np.repeat(mats, 16), "rho": np.repeat(rhos, 16)}
+    n = 4_000_000
+    _, _, eng = gpu_image(E, cfg, n)
+    c = eng.counters()
+    tau = sum(mu(orc, cfg["materials"][m], 0.6, 0b011) * float(np.float32(rho)) * k * 0.2 for m, rho, k in slabs)
+    p = math.exp(-tau)
+    z = (c["unscattered_at_epid"] - n * p) / math.sqrt(n * p * (1 - p))
+    assert abs(z) < 4, z
+
+
+def test_pixel_resolved_absorption(E, orc):
+    """Photoelectric-only parallel beam through columns of different density onto a lone
+    phosphor: each pixel's mean deposit has a closed form; x and y differ, so a transposed
+    or mirrored index fails."""
+    En = 0.03
+    cfg = synth.kerma_water()
+    cfg["physics"] = {"coupled": 0, "proc_mask": 0b010, "pcut": 0.01, "ecut": 0.2}
+    cfg["source"]["edges"] = np.array([En, En])
+    col = np.random.default_rng(7).uniform(0.1, 1.0, (4, 4))
+    cfg["phantom"] = {"kind": "direct", "shape": (4, 4, 4), "spacing": (2.5, 2.5, 1.0), "origin": (-5.0, -5.0, 0.0),
+                      "mat": np.zeros(64, np.uint8), "rho": np.tile(col.reshape(-1), 4).astype(np.float32)}
+    cfg["epid"] = {"layers": [{"mat": 2, "t": 0.003, "rho": 7.44}], "scoring": 0, "front_z": 20.0,
+                   "npx_u": 16, "npx_v": 16, "pitch_u": 0.625, "pitch_v": 0.625}
+    n = 4_000_000
+    mean, var, _ = gpu_image(E, cfg, n)
+    mw, mg = mu(orc, synth.WATER, En, 2), mu(orc, synth.GOS, En, 2)
+    absorb = 1 - math.exp(-mg * 7.44 * 0.003)
+    rho32 = col.astype(np.float32).astype(np.float64)
+    expect = np.array([[En * (0.625 ** 2 / 100.0) * math.exp(-mw * rho32[v // 4, u // 4] * 4.0) * absorb
+                        for u in range(16)] for v in range(16)])
+    p = expect / En
+    z = (mean - expect) / np.sqrt(En * En * p * (1 - p) / n)
+    assert np.all(np.abs(z) < 5), np.abs(z).max()
+    assert abs(z.mean()) < 3 / 16 and 0.8 < z.std() < 1.2
+
+
+def test_kerma_water_zgate(E, orc):
+    """Photon-only KERMA workload: GPU image against the oracle image, per 4x4-binned pixel."""
+    cfg = synth.kerma_water()
+    om, ov, *_ = oracle_image(orc, "kerma_water", cfg, 8_000_000)
+    gm, gv, _ = gpu_image(E, cfg, 80_000_000, max_chunk=1 << 24)
+    g = z_gate(gm, gv, om, ov, thr=0.10, k=4)
+    print("kerma_water z-gate", g)
+    assert g["ok"], g
+
+
+def test_coupled_small_zgate(E, orc):
+    """Coupled transport, heterogeneous phantom, 4-layer EPID: GPU vs oracle z-gate per
+    4x4-binned pixel.  Binning keeps a few hundred oracle deposits per bin: with tens of
+    events the skewed per-event energy makes the oracle's own mean and variance estimates
+    far from Gaussian and the z spread exceeds 1 for correct code."""
+    cfg = synth.coupled_hetero_small()
+    om, ov, *_ = oracle_image(orc, "coupled_small", cfg, 2_000_000)
+    gm, gv, eng = gpu_image(E, cfg, 60_000_000, max_chunk=1 << 23)
+    g = z_gate(gm, gv, om, ov, thr=0.10, k=4)
+    print("coupled_small z-gate", g, "oracle sigma-bar(4x4)", sigma_bar(rebin(om, 4), rebin(ov, 4)))
+    assert g["ok"], g
+
+
+def test_coupled_energy_ledger(E):
+    """Per history: incident energy = deposits + escapes + net rest energy, on the device."""
+    cfg = synth.coupled_hetero_small()
+    eng = E.Engine(0, seed=5).configure(cfg, batches=16, max_chunk=1 << 17, diag=True)
+    eng.bind()
+    eng.run(300_000)
+    c = eng.counters()
+    assert c["max_ledger_resid"] < 1e-9
+    assert c["e_in"] > 0 and c["e_deposited"] == pytest.approx(c["e_in"], rel=1e-12)
+    assert c["n_pair"] > 0 and c["n_moller"] > 0 and c["n_brems"] > 0 and c["n_annih"] > 0
+
+
+def test_fixed_point_bit_reproducible_across_launch_shapes(E):
+    """Fixed-point tally: the image does not depend on chunking (queue sizes, grid sizes,
+    pass structure) or on repetition."""
+    cfg = synth.coupled_hetero_small()
+    imgs = []
+    for chunk in (1 << 12, 1 << 16, 1 << 20):
+        m, v, _ = gpu_image(E, cfg, 400_000, seed=11, tally=1, max_chunk=chunk)
+        imgs.append((m, v))
+    m2, v2, _ = gpu_image(E, cfg, 400_000, seed=11, tally=1, max_chunk=1 << 16)
+    for m, v in imgs[1:] + [(m2, v2)]:
+        assert np.array_equal(m, imgs[0][0]) and np.array_equal(v, imgs[0][1])
+    assert imgs[0][0].sum() > 0
+
+
+def test_tally_modes_agree(E):
+    """Same seed, same trajectories: FP64 atomics, int64 fixed point and FP32 Kahan records
+    give the same image up to their rounding (fixed point 2^-32 MeV per deposit, FP32)."""
+    cfg = synth.coupled_hetero_small()
+    m0, v0, _ = gpu_image(E, cfg, 300_000, seed=12, tally=0)
+    m1, v1, _ = gpu_image(E, cfg, 300_000, seed=12, tally=1)
+    m2, v2, _ = gpu_image(E, cfg, 300_000, seed=12, tally=2)
+    assert m0.sum() > 0
+    np.testing.assert_allclose(m1, m0, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(m2, m0, rtol=1e-6, atol=1e-13)
+    np.testing.assert_allclose(v2, v0, rtol=1e-4, atol=1e-20)
+
+
+def test_segment_sum_is_field(E):
+    """Histories are keyed by id: an IMRT field run in one call equals the sum of its
+    segment ranges run separately (fixed point: exactly)."""
+    cfg = synth.imrt_field(shape=(64, 64, 32), spacing=0.8, npx=(96, 128), pitch=0.312)
+    cfg = synth.with_histories_scaled(cfg, 400_000)
+    cnt = cfg["source"]["aperture"]["counts"].astype(np.int64)
+    tot = int(cnt.sum())
+    eng = E.Engine(0, seed=13).configure(cfg, tally=1, batches=2, max_chunk=1 << 18)
+    eng.bind()
+    eng.run(tot)
+    whole = eng.image()[0].cpu().numpy() * tot
+    eng.reset()
+    cut = int(cnt[:17].sum())
+    eng.run(cut)
+    eng.run(tot - cut, first=cut)
+    parts = eng.image()[0].cpu().numpy() * tot
+    assert whole.sum() > 0
+    np.testing.assert_array_equal(parts, whole)
+
+
+def test_full_size_coupled_runs(E):
+    """The full 256x256x128 / 1024x768 workload runs in large chunks without device errors
+    and gives a finite, non-trivial image."""
+    cfg = synth.coupled_hetero()
+    eng = E.Engine(0, seed=3).configure(cfg, batches=64, max_chunk=1 << 24)
+    eng.bind()
+    eng.run(40_000_000)
+    m, v = eng.image()
+    m = m.cpu().numpy()
+    assert bool(np.isfinite(m).all()) and m.max() > 0
+    c = eng.counters()
+    assert c["error_word"] == 0 and c["tally_deposits"] > 0
+    # the open field (15x15 cm at the phosphor) is brighter than the region outside it
+    inner = m[512 - 64:512 + 64, 384 - 64:384 + 64].mean()
+    outer = m[:100, :100].mean()
+    assert inner > 5 * outer
+
+
+def test_sigma_bar_falls_as_inverse_sqrt_n(E):
+    """Mean relative uncertainty over the bright pixels falls as 1/sqrt(N) once every pixel
+    has hundreds of deposits."""
+    cfg = synth.coupled_hetero_small()
+    eng = E.Engine(0, seed=3).configure(cfg, batches=64, max_chunk=1 << 23)
+    eng.bind()
+    eng.run(10_000_000)
+    s1 = eng.sigma_bar(0.5)
+    eng.run(30_000_000, first=10_000_000)
+    s2 = eng.sigma_bar(0.5)
+    assert s2 == pytest.approx(s1 / 2.0, rel=0.08)
+
+
+def test_run_until_stops_at_target(E):
+    cfg = synth.kerma_water(npx=16, pitch=1.6)
+    eng = E.Engine(0, seed=4).configure(cfg, batches=64, max_chunk=1 << 22)
+    eng.bind()
+    done, sb = eng.run_until(0.05, thr=0.5, step=2_000_000, max_hist=200_000_000)
+    assert sb <= 0.05 and done <= 200_000_000
+    assert eng.sigma_bar(0.5) == pytest.approx(sb)
