@@ -33,6 +33,31 @@ OPS_PER_UNIT = {"electron_step": 310, "woodcock_step": 120, "epid_photon_step": 
 KIND = ["photon_phantom", "electron_phantom", "photon_epid", "electron_epid"]
 
 
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("csrc/kernels.hip", "csrc/device.hpp", "csrc/engine.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2510_24154_amd", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summaries
+    (FETCH_SIZE and WRITE_SIZE passes, calibrated on a plain copy), or None when no summary
+    was taken on the current kernel sources."""
+    import glob
+    sha = kernel_source_sha()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        kv = {}
+        for line in open(f):
+            parts = line.strip().split(": ", 1)
+            if len(parts) == 2:
+                kv[parts[0]] = parts[1]
+        if kv.get("traffic_kernel") == kernel and kv.get("source_sha") == sha:
+            return float(kv["traffic_bytes_per_launch"]), os.path.basename(f)
+    return None, None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,9 +115,14 @@ def main():
     avg_s = c["kernel_ms"][dom] / 1e3 / launches
     ops_per_launch = units[dom] * per[dom] / launches
     achieved = ops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
-    roof = {"bound": "alu", "kernel": "k_electron<phantom>" if dom == 1 else KIND[dom],
+    kname = "k_electron<phantom>" if dom == 1 else KIND[dom]
+    traffic, tsrc = profiled_traffic(kname)
+    roof = {"bound": "alu", "kernel": kname,
             "achieved": round(achieved, 3), "peak": round(ALU_PEAK_OPS / 1e12, 3), "unit": "Tlane-op/s",
-            "frac": round(achieved * 1e12 / ALU_PEAK_OPS, 4), "traffic": None,
+            "frac": round(achieved * 1e12 / ALU_PEAK_OPS, 4),
+            "traffic": round(traffic) if traffic else None, "traffic_unit": "bytes/launch",
+            "traffic_source": tsrc,
+            "traffic_GBps": round(traffic / avg_s / 1e9, 1) if traffic and avg_s > 0 else None,
             "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches,
             "unit_of_work": "electron condensed-history step" if dom in (1, 3) else KIND[dom],
             "units_per_launch": round(units[dom] / launches), "ops_per_unit": per[dom],
