@@ -104,10 +104,10 @@ __device__ __forceinline__ void qappend(const Params &P, int kind, bool pred, co
 // stages particles in a per-wave LDS buffer and appends them to the global queue in bulk.
 // ---------------------------------------------------------------------------------
 // A wave's staging buffers: 12 x SBUF words (structure of arrays) followed by the fill
-// count, in LDS, for electrons entering the phantom queue (e) and photons entering the
-// EPID queue (g); null when the kernel appends directly.
+// count, in LDS, for electrons entering the phantom queue (e), photons entering the EPID
+// queue (g) and electrons entering the EPID queue (ee); null when the kernel appends directly.
 struct Stages {
-    uint32_t *e, *g;
+    uint32_t *e, *g, *ee;
 };
 
 __device__ __forceinline__ void stage_put(uint32_t *w, uint32_t i, const Part &p)
@@ -135,7 +135,7 @@ __device__ __forceinline__ Part stage_get(const uint32_t *w, uint32_t i)
 // straight to the queue
 __device__ __forceinline__ void append(const Params &P, Stages S, int kind, bool pred, const Part &p)
 {
-    uint32_t *w = kind == QEP ? S.e : kind == QGE ? S.g : nullptr;
+    uint32_t *w = kind == QEP ? S.e : kind == QGE ? S.g : kind == QEE ? S.ee : nullptr;
     if (!w) {
         qappend(P, kind, pred, p);
         return;

@@ -104,7 +104,7 @@ __device__ __forceinline__ int vacuum_phantom_frame(const Params &P, Part &p)
 }
 
 // hand a particle (position in the frame of `region`) to its next queue, or let it escape
-__device__ __forceinline__ void place(const Params &P, int region, Part &c, Local &L, Stages S = Stages{nullptr, nullptr})
+__device__ __forceinline__ void place(const Params &P, int region, Part &c, Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
 {
     const bool photon = (c.flags & F_TYPE) == 0;
     int r = region;
@@ -146,7 +146,7 @@ __device__ __forceinline__ void deposit_point(const Params &P, int region, const
 
 // a new photon at the parent's position
 __device__ __forceinline__ void emit_photon(const Params &P, int region, Part &parent, float E, float u, float v, float w,
-                            Local &L, Stages S = Stages{nullptr, nullptr})
+                            Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
 {
     Part c;
     make_child(parent, c, P, 0u);
@@ -161,7 +161,7 @@ __device__ __forceinline__ void emit_photon(const Params &P, int region, Part &p
 }
 
 // two back-to-back photons of m c^2 from a positron at rest
-__device__ __forceinline__ void annihilate(const Params &P, int region, Part &pos, Local &L, Stages S = Stages{nullptr, nullptr})
+__device__ __forceinline__ void annihilate(const Params &P, int region, Part &pos, Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
 {
     const float4 r = rnd4(pos, P);
     const float ct = 2.0f * r.x - 1.0f, st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
@@ -175,7 +175,7 @@ __device__ __forceinline__ void annihilate(const Params &P, int region, Part &po
 
 // a new electron (type 1) or positron (type 2) at the parent's position
 __device__ __forceinline__ void emit_electron(const Params &P, int region, Part &parent, float T, uint32_t type, float u, float v,
-                              float w, Local &L, Stages S = Stages{nullptr, nullptr})
+                              float w, Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
 {
     Part c;
     make_child(parent, c, P, type);
@@ -255,7 +255,7 @@ __device__ __forceinline__ float highland(float T, float x, float X0)
 // Returns true while the photon lives.
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ bool photon_interact(const Params &P, int region, Part &p, const float *tab, Node n, float rproc,
-                                Local &L, Stages S = Stages{nullptr, nullptr})
+                                Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
 {
     const float fc = lerp_tab(tab + NB_PH, n), fcp = lerp_tab(tab + 2 * NB_PH, n);
     p.flags &= ~F_UNSCAT;
@@ -356,8 +356,17 @@ __global__ __launch_bounds__(WG) void k_source(Params P)
         p.flags = (slot << F_SLOT_SHIFT) | type | (type == 0 ? F_UNSCAT : 0u);
         if (P.diag) P.ein[h - P.h0] = (double)p.E;
         p.x = gx - P.ox; p.y = gy - P.oy; p.z = gz - P.oz;
-        // a source particle that starts inside the box is in the phantom
-        if (in_phantom(P, p.x, p.y, p.z)) {
+        if (!P.n_phsp) {
+            // spectrum source: every history is one photon.  It takes slot h - h0 of the photon
+            // queue directly (no atomics); one that misses the phantom box is stored where it
+            // is and placed by the Woodcock kernel when loaded.
+            if (!in_phantom(P, p.x, p.y, p.z)) {
+                Part q = p;
+                if (vacuum_phantom_frame(P, q) == 0) p = q;   // moved to its entry point
+            }
+            qstore(P.out[QGP], (uint32_t)(h - P.h0), p);
+        } else if (in_phantom(P, p.x, p.y, p.z)) {
+            // a phase-space particle that starts inside the box is in the phantom
             const bool photon = type == 0;
             qappend(P, QGP, photon, p);
             qappend(P, QEP, !photon, p);
@@ -365,6 +374,7 @@ __global__ __launch_bounds__(WG) void k_source(Params P)
             place(P, 0, p, L);
         }
     }
+    if (!P.n_phsp && blockIdx.x == 0 && threadIdx.x == 0) P.cnt_out[QGP] = (uint32_t)(P.h1 - P.h0);
     // counters of direct hits on the EPID
     if (L.entries) atomicAdd(&P.stats[S_EPID_ENTRIES], (unsigned long long)L.entries);
     if (L.unscat) atomicAdd(&P.stats[S_UNSCAT], (unsigned long long)L.unscat);
@@ -398,6 +408,7 @@ __global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
     Stages S;
     S.e = stage_base;
     S.g = stage_base + (12 * SBUF + 1);
+    S.ee = nullptr;
 
     const uint32_t n = min(P.cnt_in[QGP], P.cap[QGP]);
     Win win{0, 0, 0};
@@ -418,7 +429,14 @@ __global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
         if (act == 0) break;
         lane_iters += __popcll(act);
         wave_iters += 64;
-        if (active && !was) ++L.items;
+        if (active && !was) {
+            ++L.items;
+            if (!in_phantom(P, p.x, p.y, p.z)) {
+                // a source photon whose ray misses the box: EPID or escape
+                place(P, 0, p, L, S);
+                active = false;
+            }
+        }
         if (!active) continue;
         if (p.E != e_cached) {
             e_cached = p.E;
@@ -467,11 +485,19 @@ template __global__ void k_photon_phantom<false>(Params);
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
 {
+    // dynamic LDS: the layer tables, then per wave one staging buffer (12 x SBUF + fill) for
+    // the electrons set in motion in the EPID
     extern __shared__ float lds[];
     __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS];
     const int ntab = P.nl * 3 * NB_PH;
     const float *src = P.ph_tab + MAX_PMAT * 3 * NB_PH;
     for (int i = threadIdx.x; i < ntab; i += WG) lds[i] = src[i];
+    uint32_t *stage = (uint32_t *)(lds + ntab) + (threadIdx.x >> 6) * (12 * SBUF + 1);
+    if ((threadIdx.x & 63) == 0) stage[12 * SBUF] = 0;
+    Stages S;
+    S.e = nullptr;
+    S.g = nullptr;
+    S.ee = stage;
     if (threadIdx.x <= MAX_LAYERS) s_zl[threadIdx.x] = P.zl[threadIdx.x];
     if (threadIdx.x < MAX_LAYERS) s_rho[threadIdx.x] = P.lrho[threadIdx.x];
     __syncthreads();
@@ -484,6 +510,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
     zero(L);
     unsigned long long lane_iters = 0, wave_iters = 0;
     for (;;) {
+        stage_flush(P, S.ee, QEE, SBUF / 2);
         const bool was = active;
         refill(P, QGE, n, win, active, p);
         const unsigned long long act = __ballot(active);
@@ -515,7 +542,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
             p.x = fmaf(s, p.u, p.x);
             p.y = fmaf(s, p.v, p.y);
             p.z = fmaf(s, p.w, p.z);
-            active = photon_interact(P, 1, p, tab, nd, r.y, L);
+            active = photon_interact(P, 1, p, tab, nd, r.y, L, S);
             continue;
         }
         if (tl <= tz) {   // leaves through a lateral face
@@ -534,6 +561,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
         p.z = dl > 0 ? s_zl[l + 1] : s_zl[l];
         p.flags = (p.flags & ~F_LAYER_MASK) | ((uint32_t)nlay << F_LAYER_SHIFT);
     }
+    stage_flush(P, S.ee, QEE, 1);
     flush_stats(P, L, S_EPID_PH_STEPS, QGE, lane_iters, wave_iters);
 }
 
@@ -1031,7 +1059,7 @@ size_t lds_bytes(int kind, const Params &P)
 {
     switch (kind) {
     case QGP: return (size_t)(WG / 64) * 2 * (12 * SBUF + 1) * 4 + (PH_TAB_LDS ? (size_t)(P.nmat_ph * 3 + 1) * NB_PH * 4 : 0);
-    case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float);
+    case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float) + (size_t)(WG / 64) * (12 * SBUF + 1) * 4;
     case QEP: return (size_t)P.nmat_ph * 3 * NB_EL * sizeof(float);
     default: return (size_t)P.nl * 3 * NB_EL * sizeof(float);
     }
