@@ -61,20 +61,19 @@ __device__ __forceinline__ void make_child(Part &parent, Part &c, const Params &
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ Part qload(const Queue &q, uint32_t i)
 {
+    const uint4 a = q.a[i], b = q.b[i], c = q.c[i];
     Part p;
-    p.x = q.x[i]; p.y = q.y[i]; p.z = q.z[i];
-    p.u = q.u[i]; p.v = q.v[i]; p.w = q.w[i];
-    p.E = q.E[i];
-    p.hist = q.hist[i]; p.plo = q.plo[i]; p.phi = q.phi[i]; p.draw = q.draw[i]; p.flags = q.flags[i];
+    p.x = __uint_as_float(a.x); p.y = __uint_as_float(a.y); p.z = __uint_as_float(a.z); p.u = __uint_as_float(a.w);
+    p.v = __uint_as_float(b.x); p.w = __uint_as_float(b.y); p.E = __uint_as_float(b.z); p.hist = b.w;
+    p.plo = c.x; p.phi = c.y; p.draw = c.z; p.flags = c.w;
     return p;
 }
 
 __device__ __forceinline__ void qstore(const Queue &q, uint32_t i, const Part &p)
 {
-    q.x[i] = p.x; q.y[i] = p.y; q.z[i] = p.z;
-    q.u[i] = p.u; q.v[i] = p.v; q.w[i] = p.w;
-    q.E[i] = p.E;
-    q.hist[i] = p.hist; q.plo[i] = p.plo; q.phi[i] = p.phi; q.draw[i] = p.draw; q.flags[i] = p.flags;
+    q.a[i] = make_uint4(__float_as_uint(p.x), __float_as_uint(p.y), __float_as_uint(p.z), __float_as_uint(p.u));
+    q.b[i] = make_uint4(__float_as_uint(p.v), __float_as_uint(p.w), __float_as_uint(p.E), p.hist);
+    q.c[i] = make_uint4(p.plo, p.phi, p.draw, p.flags);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -110,24 +109,21 @@ struct Stages {
     uint32_t *e, *g, *ee;
 };
 
+// a staging buffer holds its particles as three arrays of SBUF 16-byte words, like a queue
 __device__ __forceinline__ void stage_put(uint32_t *w, uint32_t i, const Part &p)
 {
-    w[0 * SBUF + i] = __float_as_uint(p.x); w[1 * SBUF + i] = __float_as_uint(p.y);
-    w[2 * SBUF + i] = __float_as_uint(p.z); w[3 * SBUF + i] = __float_as_uint(p.u);
-    w[4 * SBUF + i] = __float_as_uint(p.v); w[5 * SBUF + i] = __float_as_uint(p.w);
-    w[6 * SBUF + i] = __float_as_uint(p.E); w[7 * SBUF + i] = p.hist;
-    w[8 * SBUF + i] = p.plo; w[9 * SBUF + i] = p.phi; w[10 * SBUF + i] = p.draw; w[11 * SBUF + i] = p.flags;
+    uint4 *w4 = (uint4 *)w;
+    w4[i] = make_uint4(__float_as_uint(p.x), __float_as_uint(p.y), __float_as_uint(p.z), __float_as_uint(p.u));
+    w4[SBUF + i] = make_uint4(__float_as_uint(p.v), __float_as_uint(p.w), __float_as_uint(p.E), p.hist);
+    w4[2 * SBUF + i] = make_uint4(p.plo, p.phi, p.draw, p.flags);
 }
 
-__device__ __forceinline__ Part stage_get(const uint32_t *w, uint32_t i)
+__device__ __forceinline__ void stage_copy(const Queue &q, uint32_t g, const uint32_t *w, uint32_t i)
 {
-    Part p;
-    p.x = __uint_as_float(w[0 * SBUF + i]); p.y = __uint_as_float(w[1 * SBUF + i]);
-    p.z = __uint_as_float(w[2 * SBUF + i]); p.u = __uint_as_float(w[3 * SBUF + i]);
-    p.v = __uint_as_float(w[4 * SBUF + i]); p.w = __uint_as_float(w[5 * SBUF + i]);
-    p.E = __uint_as_float(w[6 * SBUF + i]); p.hist = w[7 * SBUF + i];
-    p.plo = w[8 * SBUF + i]; p.phi = w[9 * SBUF + i]; p.draw = w[10 * SBUF + i]; p.flags = w[11 * SBUF + i];
-    return p;
+    const uint4 *w4 = (const uint4 *)w;
+    q.a[g] = w4[i];
+    q.b[g] = w4[SBUF + i];
+    q.c[g] = w4[2 * SBUF + i];
 }
 
 // append one particle per lane with `pred`, through the wave's staging buffer when the kind
@@ -141,7 +137,7 @@ __device__ __forceinline__ void append(const Params &P, Stages S, int kind, bool
         return;
     }
     if (!pred) return;
-    const uint32_t i = atomicAdd(w + 12 * SBUF, 1u);
+    const uint32_t i = __hip_atomic_fetch_add(w + 12 * SBUF, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     if (i < SBUF) {
         stage_put(w, i, p);
     } else {
@@ -153,24 +149,25 @@ __device__ __forceinline__ void append(const Params &P, Stages S, int kind, bool
 
 // move a wave's staged particles to the global queue `kind` when at least `minfill` are
 // waiting; call with the wave converged
+// LDS instructions of one wave complete in order, so the buffer needs no memory fence: the
+// fill count is read and reset with wave-scope atomics, and wave barriers keep the compiler
+// from moving the staged reads and writes across them (a fence would also wait for every
+// outstanding global load and store of the wave).
 __device__ __forceinline__ void stage_flush(const Params &P, uint32_t *w, int kind, uint32_t minfill)
 {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const uint32_t n = min(w[12 * SBUF], (uint32_t)SBUF);
+    const uint32_t n =
+        min(__hip_atomic_load(w + 12 * SBUF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT), (uint32_t)SBUF);
     if (n == 0 || n < minfill) return;
     uint32_t base = 0;
     if (lane_id() == 0) base = atomicAdd(&P.cnt_out[kind], n);
     base = __shfl(base, 0);
     for (uint32_t i = lane_id(); i < n; i += 64) {
-        const Part q = stage_get(w, i);
-        if (base + i < P.cap[kind]) qstore(P.out[kind], base + i, q);
+        if (base + i < P.cap[kind]) stage_copy(P.out[kind], base + i, w, i);
         else atomicOr(P.err, ERR_QUEUE);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (lane_id() == 0) w[12 * SBUF] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane_id() == 0) __hip_atomic_store(w + 12 * SBUF, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     __builtin_amdgcn_wave_barrier();
 }
 

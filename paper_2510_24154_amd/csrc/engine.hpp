@@ -17,6 +17,7 @@ constexpr int MAX_SLOTS = 128;     // variance batches per chunk
 constexpr int WG = 256;            // threads per workgroup of the transport kernels
 constexpr int WIN = 128;           // queue items a wave claims per atomic
 constexpr int SBUF = 64;           // particles a wave stages in LDS per queue kind before one bulk append
+constexpr int SSTRIDE = 12 * SBUF + 4; // words of one LDS staging buffer: 3 x SBUF 16-byte words, the fill count, padding
 constexpr int ITEMS_PER_LANE = 8;  // a pass launches enough waves for about this many items per lane:
                                    // a wave lives as long as its slowest particle, so thinner waves waste lanes
 
@@ -49,9 +50,11 @@ constexpr float SKIN = 0.05f;                // a boundary-limited step is at le
 constexpr float DE_FRAC = 0.9f;              // a step keeps at least 90% of its start energy
 constexpr int MAX_E_STEPS = 100000;          // per electron and launch; more is an error
 
-struct Queue {                 // structure-of-arrays particle store
-    float *x, *y, *z, *u, *v, *w, *E;
-    uint32_t *hist, *plo, *phi, *draw, *flags;
+// A queued particle is three 16-byte words kept in three arrays of `cap` words
+// (a: x y z u, b: v w E hist, c: plo phi draw flags): a lane moves a particle with three
+// 128-bit accesses, and a queue costs a kernel three base pointers.
+struct Queue {
+    uint4 *a, *b, *c;
 };
 
 struct Params {
@@ -70,6 +73,7 @@ struct Params {
     float ox, oy, oz;           // global position of the local origin
     float chord;                // longer than any straight path inside the box
     double ddx, ddy, ddz;       // voxel spacing in FP64 (electron positions are FP64)
+    double iddx, iddy, iddz;    // and its inverse
     float smin_ph;              // minimum boundary-limited electron step in the phantom
     const uint32_t *vox;        // packed density (bits 31..2) | material (bits 1..0)
 

@@ -635,10 +635,8 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
         for (int k = 0; k < NQ; ++k) {
             Queue &Q = c->qs[b][k];
             const size_t n = L.cap[k];
-            float **fp[7] = {&Q.x, &Q.y, &Q.z, &Q.u, &Q.v, &Q.w, &Q.E};
-            for (int f = 0; f < 7; ++f) { *fp[f] = (float *)q; q += n * 4; }
-            uint32_t **up5[5] = {&Q.hist, &Q.plo, &Q.phi, &Q.draw, &Q.flags};
-            for (int f = 0; f < 5; ++f) { *up5[f] = (uint32_t *)q; q += n * 4; }
+            uint4 **fp[3] = {&Q.a, &Q.b, &Q.c};
+            for (int f = 0; f < 3; ++f) { *fp[f] = (uint4 *)q; q += n * 16; }
         }
     for (int k = 0; k < NQ; ++k) P.cap[k] = L.cap[k];
     char *ctl = w + L.ctl.off;
@@ -655,6 +653,7 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
     P.ox = c->origin[0]; P.oy = c->origin[1]; P.oz = c->origin[2];
     P.chord = P.Lx + P.Ly + P.Lz + 1.0f;
     P.ddx = c->spacing[0]; P.ddy = c->spacing[1]; P.ddz = c->spacing[2];
+    P.iddx = 1.0 / P.ddx; P.iddy = 1.0 / P.ddy; P.iddz = 1.0 / P.ddz;
     P.smin_ph = SKIN * std::min(c->spacing[0], std::min(c->spacing[1], c->spacing[2]));
     P.vox = (const uint32_t *)(w + L.vox.off);
     P.nl = (int)c->layers.size();

@@ -243,11 +243,12 @@ __device__ __forceinline__ float highland(float T, float x, float X0)
 {
     if (!(x > 0.0f)) return 0.0f;
     const float E = T + MEC2F;
+    const float iE = __frcp_rn(E);
     const float pc2 = T * (T + 2.0f * MEC2F);
-    const float bcp = pc2 / E, b2 = pc2 / (E * E);
-    const float r = x / X0;
-    const float br = fmaxf(0.0f, 1.0f + 0.038f * __logf(r / b2));
-    return 13.6f / bcp * sqrtf(r) * br;
+    const float b2 = pc2 * iE * iE;
+    const float r = __fdividef(x, X0);
+    const float br = fmaxf(0.0f, 1.0f + 0.038f * __logf(__fdividef(r, b2)));
+    return __fdividef(13.6f * E, pc2) * sqrtf(r) * br;
 }
 
 // ---------------------------------------------------------------------------------
@@ -384,13 +385,13 @@ __global__ __launch_bounds__(WG) void k_source(Params P)
 // photons in the phantom: Woodcock tracking
 // ---------------------------------------------------------------------------------
 template <bool TAB_LDS>
-__global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
+__global__ __launch_bounds__(WG, 6) void k_photon_phantom(Params P)
 {
-    // dynamic LDS: per wave two staging buffers of 12 x SBUF words + a fill count, then the
-    // tables when they are staged
-    extern __shared__ float lds[];
+    // dynamic LDS: per wave two staging buffers of SSTRIDE words, then the tables when they
+    // are staged
+    extern __shared__ __align__(16) float lds[];
     const int wave = threadIdx.x >> 6;
-    constexpr int SWORDS = 2 * (12 * SBUF + 1);
+    constexpr int SWORDS = 2 * SSTRIDE;
     uint32_t *stage_base = (uint32_t *)lds + (size_t)wave * SWORDS;
     float *tabs = lds + (WG / 64) * SWORDS;
     const int ntab = P.nmat_ph * 3 * NB_PH;
@@ -400,14 +401,14 @@ __global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
     }
     if (threadIdx.x < 64) {
         const int w = threadIdx.x >> 4, k = (threadIdx.x >> 3) & 1;
-        if ((threadIdx.x & 7) == 0 && w < WG / 64) ((uint32_t *)lds)[w * SWORDS + k * (12 * SBUF + 1) + 12 * SBUF] = 0;
+        if ((threadIdx.x & 7) == 0 && w < WG / 64) ((uint32_t *)lds)[w * SWORDS + k * SSTRIDE + 12 * SBUF] = 0;
     }
     __syncthreads();
     const float *tab = TAB_LDS ? tabs : P.ph_tab;
     const float *maj = TAB_LDS ? tabs + ntab : P.ph_maj;
     Stages S;
     S.e = stage_base;
-    S.g = stage_base + (12 * SBUF + 1);
+    S.g = stage_base + SSTRIDE;
     S.ee = nullptr;
 
     const uint32_t n = min(P.cnt_in[QGP], P.cap[QGP]);
@@ -485,14 +486,14 @@ template __global__ void k_photon_phantom<false>(Params);
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
 {
-    // dynamic LDS: the layer tables, then per wave one staging buffer (12 x SBUF + fill) for
-    // the electrons set in motion in the EPID
-    extern __shared__ float lds[];
+    // dynamic LDS: the layer tables, then per wave one staging buffer (SSTRIDE words) for the
+    // electrons set in motion in the EPID
+    extern __shared__ __align__(16) float lds[];
     __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS];
     const int ntab = P.nl * 3 * NB_PH;
     const float *src = P.ph_tab + MAX_PMAT * 3 * NB_PH;
     for (int i = threadIdx.x; i < ntab; i += WG) lds[i] = src[i];
-    uint32_t *stage = (uint32_t *)(lds + ntab) + (threadIdx.x >> 6) * (12 * SBUF + 1);
+    uint32_t *stage = (uint32_t *)(lds + ntab) + (threadIdx.x >> 6) * SSTRIDE;
     if ((threadIdx.x & 63) == 0) stage[12 * SBUF] = 0;
     Stages S;
     S.e = nullptr;
@@ -571,7 +572,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
 template <bool EPID>
 __global__ __launch_bounds__(WG) void k_electron(Params P)
 {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS], s_smin[MAX_LAYERS], s_x0[MAX_PMAT + MAX_LAYERS];
     const int nm = EPID ? P.nl : P.nmat_ph;
     const float *src = P.el_tab + (EPID ? MAX_PMAT : 0) * 3 * NB_EL;
@@ -623,9 +624,9 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
         double lo0, hi0, lo1, hi1, lo2, hi2;
         int m, layer = -1;
         if (!EPID) {
-            const int ix = min(max((int)(px / P.ddx), 0), P.nx - 1);
-            const int iy = min(max((int)(py / P.ddy), 0), P.ny - 1);
-            const int iz = min(max((int)(pz / P.ddz), 0), P.nz - 1);
+            const int ix = min(max((int)(px * P.iddx), 0), P.nx - 1);
+            const int iy = min(max((int)(py * P.iddy), 0), P.ny - 1);
+            const int iz = min(max((int)(pz * P.iddz), 0), P.nz - 1);
             const uint32_t word = P.vox[((size_t)iz * P.ny + iy) * P.nx + ix];
             rho = __uint_as_float(word & ~3u);
             m = (int)(word & 3u);
@@ -645,11 +646,13 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
             lo2 = s_zl[l]; hi2 = s_zl[l + 1];
             smin = s_smin[l];
         }
-        double dg = INFINITY;
-        if (p.u > 0.0f) dg = fmin(dg, (hi0 - px) / p.u); else if (p.u < 0.0f) dg = fmin(dg, (lo0 - px) / p.u);
-        if (p.v > 0.0f) dg = fmin(dg, (hi1 - py) / p.v); else if (p.v < 0.0f) dg = fmin(dg, (lo1 - py) / p.v);
-        if (p.w > 0.0f) dg = fmin(dg, (hi2 - pz) / p.w); else if (p.w < 0.0f) dg = fmin(dg, (lo2 - pz) / p.w);
-        const float sg = fmaxf((float)fmax(dg, 0.0) + NUDGE, smin);
+        // distance to the cell faces: the offset to the face is taken in FP64, then the small
+        // difference is divided in FP32
+        float dg = INFINITY;
+        if (p.u != 0.0f) dg = fminf(dg, (float)((p.u > 0.0f ? hi0 : lo0) - px) * __frcp_rn(p.u));
+        if (p.v != 0.0f) dg = fminf(dg, (float)((p.v > 0.0f ? hi1 : lo1) - py) * __frcp_rn(p.v));
+        if (p.w != 0.0f) dg = fminf(dg, (float)((p.w > 0.0f ? hi2 : lo2) - pz) * __frcp_rn(p.w));
+        const float sg = fmaxf(fmaxf(dg, 0.0f) + NUDGE, smin);
         float T = p.E;
         if (!(rho > 0.0f)) {
             px += (double)sg * p.u;
@@ -665,7 +668,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
             const float R9 = lerp_tab(tab, n9);
             const float4 r = rnd4(p, P);
             const float irho = 1.0f / rho;
-            const float s_hard = sh > 0.0f ? -__logf(r.x) / (rho * sh) : INFINITY;
+            const float s_hard = sh > 0.0f ? __fdividef(-__logf(r.x), rho * sh) : INFINITY;
             const float s_de = (R0 - R9) * irho;
             const float s_pix = (EPID && layer == P.scoring) ? P.s_pix : INFINITY;
             const float s = fminf(fminf(s_hard, s_de), fminf(sg, s_pix));
@@ -682,7 +685,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                     if (tab[mid] <= Rt) lo = mid; else hi = mid;
                 }
                 const float d = tab[lo + 1] - tab[lo];
-                const float f = d > 0.0f ? fminf(fmaxf((Rt - tab[lo]) / d, 0.0f), 1.0f) : 0.0f;
+                const float f = d > 0.0f ? fminf(fmaxf(__fdividef(Rt - tab[lo], d), 0.0f), 1.0f) : 0.0f;
                 T1 = fminf(__expf(P.el_lnT0 + ((float)lo + f) / P.el_idl), T);
             }
             // hinge point: the step's continuous loss is deposited there
@@ -1058,8 +1061,8 @@ hipError_t launch_source(const Params &P, hipStream_t s)
 size_t lds_bytes(int kind, const Params &P)
 {
     switch (kind) {
-    case QGP: return (size_t)(WG / 64) * 2 * (12 * SBUF + 1) * 4 + (PH_TAB_LDS ? (size_t)(P.nmat_ph * 3 + 1) * NB_PH * 4 : 0);
-    case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float) + (size_t)(WG / 64) * (12 * SBUF + 1) * 4;
+    case QGP: return (size_t)(WG / 64) * 2 * SSTRIDE * 4 + (PH_TAB_LDS ? (size_t)(P.nmat_ph * 3 + 1) * NB_PH * 4 : 0);
+    case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float) + (size_t)(WG / 64) * SSTRIDE * 4;
     case QEP: return (size_t)P.nmat_ph * 3 * NB_EL * sizeof(float);
     default: return (size_t)P.nl * 3 * NB_EL * sizeof(float);
     }
