@@ -237,7 +237,8 @@ epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *dev_ctr, uint32
  * transfer at kinetic energy p0; kind 2 bremsstrahlung photon energy at p0; kind 3
  * multiple-scattering polar angle for kinetic energy p0 over p1 g/cm^2 of material p2;
  * kind 4 the source: 8 floats (x y z u v w E type) per history starting at history
- * p0.  n samples into dev_out. */
+ * p0; kind 5 the azimuth uniform that accompanies a kind-0 sample (uniform on (0, 1)).
+ * n samples into dev_out. */
 epidmc_status epidmc_debug_sample(epidmc_ctx *c, int kind, double p0, double p1, double p2, float *dev_out,
                                   uint64_t n, void *stream);
 /* The device cross-section tables evaluated at energies: kind 0 photon mu/rho of

@@ -45,13 +45,23 @@ __device__ __forceinline__ float4 rnd4(Part &p, const Params &P)
     return make_float4(u01(r.x), u01(r.y), u01(r.z), u01(r.w));
 }
 
-// a secondary's stream: 64 bits of the parent's stream become its particle id
-__device__ __forceinline__ void make_child(Part &parent, Part &c, const Params &P, uint32_t type)
+// A secondary's particle id: a 64-bit mix of its parent's id and draw counter, after which
+// the parent's counter advances.  Siblings get distinct ids (the draw counter differs and the
+// mix is a bijection of 64-bit words); ids of unrelated particles of one history coincide
+// with probability about n^2 / 2^65.  The mix is the SplitMix64 finaliser (Steele, Lea and
+// Flood, OOPSLA 2014); an id only has to be distinct, since Philox decorrelates counters.
+__device__ __forceinline__ void make_child(Part &parent, Part &c, uint32_t type)
 {
-    const uint4 r = philox10(parent.draw++, parent.plo, parent.phi, parent.hist, P.key0, P.key1);
+    unsigned long long x = (((unsigned long long)parent.phi << 32) | parent.plo) ^
+                           ((unsigned long long)(parent.draw++) * 0x9E3779B97F4A7C15ull);
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 31;
     c.hist = parent.hist;
-    c.plo = r.x;
-    c.phi = r.y;
+    c.plo = (uint32_t)x;
+    c.phi = (uint32_t)(x >> 32);
     c.draw = 0;
     c.flags = (parent.flags & ~(F_TYPE | F_UNSCAT | F_LAYER_MASK)) | type;
 }
@@ -78,6 +88,9 @@ __device__ __forceinline__ void qstore(const Queue &q, uint32_t i, const Part &p
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// the wave's index in its workgroup, as a scalar (wave-uniform) value
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 // Append to the next-iteration queue of `kind`: the lanes currently executing that have
 // `pred` set take consecutive slots with a single atomic per wave.  Valid in divergent
 // code: the ballot only sees the executing lanes and the leader is one of them.
@@ -102,44 +115,48 @@ __device__ __forceinline__ void qappend(const Params &P, int kind, bool pred, co
 // resource (they serialise beyond the XCD caches), so a kernel whose lanes append often
 // stages particles in a per-wave LDS buffer and appends them to the global queue in bulk.
 // ---------------------------------------------------------------------------------
-// A wave's staging buffers: 12 x SBUF words (structure of arrays) followed by the fill
-// count, in LDS, for electrons entering the phantom queue (e), photons entering the EPID
-// queue (g) and electrons entering the EPID queue (ee); null when the kernel appends directly.
+// A wave's staging buffers, one per queue kind that the kernel appends to often (null:
+// append straight to the queue).  A buffer holds `sb` particles as three arrays of sb
+// 16-byte words, then the fill count, then padding to 16 bytes: stage_words(sb) words.
 struct Stages {
-    uint32_t *e, *g, *ee;
+    uint32_t *w[NQ];
+    uint32_t sb;
 };
 
-// a staging buffer holds its particles as three arrays of SBUF 16-byte words, like a queue
-__device__ __forceinline__ void stage_put(uint32_t *w, uint32_t i, const Part &p)
+__host__ __device__ constexpr int stage_words(int sb) { return 12 * sb + 4; }
+
+__device__ __forceinline__ Stages no_stages() { return Stages{{nullptr, nullptr, nullptr, nullptr}, 0}; }
+
+__device__ __forceinline__ void stage_put(uint32_t *w, uint32_t sb, uint32_t i, const Part &p)
 {
     uint4 *w4 = (uint4 *)w;
     w4[i] = make_uint4(__float_as_uint(p.x), __float_as_uint(p.y), __float_as_uint(p.z), __float_as_uint(p.u));
-    w4[SBUF + i] = make_uint4(__float_as_uint(p.v), __float_as_uint(p.w), __float_as_uint(p.E), p.hist);
-    w4[2 * SBUF + i] = make_uint4(p.plo, p.phi, p.draw, p.flags);
+    w4[sb + i] = make_uint4(__float_as_uint(p.v), __float_as_uint(p.w), __float_as_uint(p.E), p.hist);
+    w4[2 * sb + i] = make_uint4(p.plo, p.phi, p.draw, p.flags);
 }
 
-__device__ __forceinline__ void stage_copy(const Queue &q, uint32_t g, const uint32_t *w, uint32_t i)
+__device__ __forceinline__ void stage_copy(const Queue &q, uint32_t g, const uint32_t *w, uint32_t sb, uint32_t i)
 {
     const uint4 *w4 = (const uint4 *)w;
     q.a[g] = w4[i];
-    q.b[g] = w4[SBUF + i];
-    q.c[g] = w4[2 * SBUF + i];
+    q.b[g] = w4[sb + i];
+    q.c[g] = w4[2 * sb + i];
 }
 
 // append one particle per lane with `pred`, through the wave's staging buffer when the kind
 // has one; valid in divergent code (the slot comes from an LDS atomic); a full buffer spills
 // straight to the queue
-__device__ __forceinline__ void append(const Params &P, Stages S, int kind, bool pred, const Part &p)
+__device__ __forceinline__ void append(const Params &P, const Stages &S, int kind, bool pred, const Part &p)
 {
-    uint32_t *w = kind == QEP ? S.e : kind == QGE ? S.g : kind == QEE ? S.ee : nullptr;
+    uint32_t *w = S.w[kind];
     if (!w) {
         qappend(P, kind, pred, p);
         return;
     }
     if (!pred) return;
-    const uint32_t i = __hip_atomic_fetch_add(w + 12 * SBUF, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    if (i < SBUF) {
-        stage_put(w, i, p);
+    const uint32_t i = __hip_atomic_fetch_add(w + 12 * S.sb, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (i < S.sb) {
+        stage_put(w, S.sb, i, p);
     } else {
         const uint32_t g = atomicAdd(&P.cnt_out[kind], 1u);
         if (g < P.cap[kind]) qstore(P.out[kind], g, p);
@@ -147,28 +164,54 @@ __device__ __forceinline__ void append(const Params &P, Stages S, int kind, bool
     }
 }
 
-// move a wave's staged particles to the global queue `kind` when at least `minfill` are
-// waiting; call with the wave converged
+// move a wave's staged particles of `kind` to the global queue when at least `minfill` are
+// waiting; call with the wave converged.
 // LDS instructions of one wave complete in order, so the buffer needs no memory fence: the
 // fill count is read and reset with wave-scope atomics, and wave barriers keep the compiler
 // from moving the staged reads and writes across them (a fence would also wait for every
 // outstanding global load and store of the wave).
-__device__ __forceinline__ void stage_flush(const Params &P, uint32_t *w, int kind, uint32_t minfill)
+__device__ __forceinline__ void stage_flush(const Params &P, const Stages &S, int kind, uint32_t minfill)
 {
+    uint32_t *w = S.w[kind];
+    if (!w) return;
     __builtin_amdgcn_wave_barrier();
     const uint32_t n =
-        min(__hip_atomic_load(w + 12 * SBUF, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT), (uint32_t)SBUF);
+        min(__hip_atomic_load(w + 12 * S.sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT), S.sb);
     if (n == 0 || n < minfill) return;
     uint32_t base = 0;
     if (lane_id() == 0) base = atomicAdd(&P.cnt_out[kind], n);
     base = __shfl(base, 0);
     for (uint32_t i = lane_id(); i < n; i += 64) {
-        if (base + i < P.cap[kind]) stage_copy(P.out[kind], base + i, w, i);
+        if (base + i < P.cap[kind]) stage_copy(P.out[kind], base + i, w, S.sb, i);
         else atomicOr(P.err, ERR_QUEUE);
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane_id() == 0) __hip_atomic_store(w + 12 * SBUF, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (lane_id() == 0) __hip_atomic_store(w + 12 * S.sb, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     __builtin_amdgcn_wave_barrier();
+}
+
+// flush every staged kind (at least `minfill` waiting); wave converged
+__device__ __forceinline__ void stage_flush_all(const Params &P, const Stages &S, uint32_t minfill)
+{
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) stage_flush(P, S, k, minfill);
+}
+
+// carve a wave's staging buffers for the kinds in `mask` out of LDS at `base` (16-byte
+// aligned) and clear their fill counts; returns the words used
+__device__ __forceinline__ int stage_carve(Stages &S, uint32_t *base, unsigned mask, uint32_t sb)
+{
+    S = no_stages();
+    S.sb = sb;
+    int used = 0;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+        if (mask & (1u << k)) {
+            S.w[k] = base + used;
+            if (lane_id() == 0) S.w[k][12 * sb] = 0;
+            used += stage_words(sb);
+        }
+    return used;
 }
 
 // Wave-uniform window of queue items claimed WIN at a time.
@@ -177,11 +220,15 @@ struct Win {
     int done;
 };
 
-// Give every idle lane of a converged wave the next unclaimed particle of queue `kind`.
-__device__ __forceinline__ void refill(const Params &P, int kind, uint32_t n, Win &win, bool &active, Part &p)
+constexpr uint32_t NO_ITEM = 0xFFFFFFFFu;
+
+// Give the lanes of a converged wave that `want` an item consecutive unclaimed items of
+// queue `kind` (of n), claimed from the global head WIN at a time; returns this lane's
+// item or NO_ITEM when the queue is exhausted.
+__device__ __forceinline__ uint32_t claim(const Params &P, int kind, uint32_t n, Win &win, bool want)
 {
-    const Queue &q = P.in[kind];
-    unsigned long long need = __ballot(!active);
+    uint32_t item = NO_ITEM;
+    unsigned long long need = __ballot(want);
     while (need) {
         if (win.b >= win.e) {
             if (win.done) break;
@@ -194,12 +241,20 @@ __device__ __forceinline__ void refill(const Params &P, int kind, uint32_t n, Wi
         }
         const uint32_t avail = win.e - win.b;
         const uint32_t rank = (uint32_t)__popcll(need & __lanemask_lt());
-        if (!active && rank < avail) {
-            p = qload(q, win.b + rank);
-            active = true;
-        }
+        if (((need >> lane_id()) & 1ull) && rank < avail) item = win.b + rank;
         win.b += min((uint32_t)__popcll(need), avail);
-        need = __ballot(!active);
+        need = __ballot(want && item == NO_ITEM);
+    }
+    return item;
+}
+
+// Give every idle lane of a converged wave the next unclaimed particle of queue `kind`.
+__device__ __forceinline__ void refill(const Params &P, int kind, uint32_t n, Win &win, bool &active, Part &p)
+{
+    const uint32_t i = claim(P, kind, n, win, !active);
+    if (i != NO_ITEM) {
+        p = qload(P.in[kind], i);
+        active = true;
     }
 }
 

@@ -17,7 +17,7 @@ constexpr int MAX_SLOTS = 128;     // variance batches per chunk
 constexpr int WG = 256;            // threads per workgroup of the transport kernels
 constexpr int WIN = 128;           // queue items a wave claims per atomic
 constexpr int SBUF = 64;           // particles a wave stages in LDS per queue kind before one bulk append
-constexpr int SSTRIDE = 12 * SBUF + 4; // words of one LDS staging buffer: 3 x SBUF 16-byte words, the fill count, padding
+constexpr int SBUF_E = 16;         // the same for the electron kernels, whose appends are rarer
 constexpr int ITEMS_PER_LANE = 8;  // a pass launches enough waves for about this many items per lane:
                                    // a wave lives as long as its slowest particle, so thinner waves waste lanes
 

@@ -1010,12 +1010,12 @@ extern "C" epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *ctr,
 extern "C" epidmc_status epidmc_debug_sample(epidmc_ctx *c, int kind, double p0, double p1, double p2, float *out,
                                              uint64_t n, void *stream)
 {
-    if (!c || !out || n == 0 || kind < 0 || kind > 4) return EPIDMC_E_ARG;
+    if (!c || !out || n == 0 || kind < 0 || kind > 5) return EPIDMC_E_ARG;
     Params P = c->P;
     if (kind == 4) REQUIRE(c->bound, EPIDMC_E_NOT_READY, "source probe needs a bound workspace");
     P.key0 = (uint32_t)c->seed;
     P.key1 = (uint32_t)(c->seed >> 32);
-    if (kind == 0) REQUIRE(p0 > 0 && p0 <= 50, EPIDMC_E_RANGE, "energy in (0, 50]");
+    if (kind == 0 || kind == 5) REQUIRE(p0 > 0 && p0 <= 50, EPIDMC_E_RANGE, "energy in (0, 50]");
     if (kind == 1) REQUIRE(p0 > 2 * WCUT && p0 <= 50, EPIDMC_E_RANGE, "Moller needs T > 0.4 MeV");
     if (kind == 2) REQUIRE(p0 > KCUT && p0 <= 50, EPIDMC_E_RANGE, "bremsstrahlung needs T > 10 keV");
     if (kind == 3) REQUIRE(p0 > 0 && p1 >= 0 && p2 > 0, EPIDMC_E_RANGE, "scattering arguments");

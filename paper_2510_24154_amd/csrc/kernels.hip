@@ -104,7 +104,7 @@ __device__ __forceinline__ int vacuum_phantom_frame(const Params &P, Part &p)
 }
 
 // hand a particle (position in the frame of `region`) to its next queue, or let it escape
-__device__ __forceinline__ void place(const Params &P, int region, Part &c, Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
+__device__ __forceinline__ void place(const Params &P, int region, Part &c, Local &L, Stages S = no_stages())
 {
     const bool photon = (c.flags & F_TYPE) == 0;
     int r = region;
@@ -146,10 +146,10 @@ __device__ __forceinline__ void deposit_point(const Params &P, int region, const
 
 // a new photon at the parent's position
 __device__ __forceinline__ void emit_photon(const Params &P, int region, Part &parent, float E, float u, float v, float w,
-                            Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
+                            Local &L, Stages S = no_stages())
 {
     Part c;
-    make_child(parent, c, P, 0u);
+    make_child(parent, c, 0u);
     c.x = parent.x; c.y = parent.y; c.z = parent.z;
     c.u = u; c.v = v; c.w = w;
     c.E = E;
@@ -161,7 +161,7 @@ __device__ __forceinline__ void emit_photon(const Params &P, int region, Part &p
 }
 
 // two back-to-back photons of m c^2 from a positron at rest
-__device__ __forceinline__ void annihilate(const Params &P, int region, Part &pos, Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
+__device__ __forceinline__ void annihilate(const Params &P, int region, Part &pos, Local &L, Stages S = no_stages())
 {
     const float4 r = rnd4(pos, P);
     const float ct = 2.0f * r.x - 1.0f, st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
@@ -175,10 +175,10 @@ __device__ __forceinline__ void annihilate(const Params &P, int region, Part &po
 
 // a new electron (type 1) or positron (type 2) at the parent's position
 __device__ __forceinline__ void emit_electron(const Params &P, int region, Part &parent, float T, uint32_t type, float u, float v,
-                              float w, Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
+                              float w, Local &L, Stages S = no_stages())
 {
     Part c;
-    make_child(parent, c, P, type);
+    make_child(parent, c, type);
     c.x = parent.x; c.y = parent.y; c.z = parent.z;
     c.u = u; c.v = v; c.w = w;
     c.E = T;
@@ -193,28 +193,55 @@ __device__ __forceinline__ void emit_electron(const Params &P, int region, Part 
 // ---------------------------------------------------------------------------------
 // samplers
 // ---------------------------------------------------------------------------------
-// Klein-Nishina eps = E'/E by the Butcher-Messel split of (1/eps + eps) into a 1/eps part and
-// an eps part, with the rejection function 1 - eps sin^2/(1 + eps^2).  Also returns the
-// azimuth uniform of the accepted trial.
+// Klein-Nishina eps = E'/E by the Butcher-Messel split of (1/eps + eps) into a 1/eps part
+// (eps = eps0^u) and an eps part (eps^2 uniform on [eps0^2, 1]), with the rejection function
+// 1 - eps sin^2 / (1 + eps^2).  A trial takes two uniforms: u1 picks the part with
+// probability a1 / (a1 + a2) and, rescaled to (0, 1) within it, gives the trial eps; u2 is
+// the acceptance variate, and on acceptance u2 / g is uniform on (0, 1) independently of
+// eps, which gives the azimuth.
+struct KN {
+    float k, e0, e02, a1, pa, ipa, iqa;
+};
+
+__device__ __forceinline__ KN kn_setup(float E)
+{
+    KN c;
+    c.k = E * (1.0f / MEC2F);
+    const float d = fmaf(2.0f, c.k, 1.0f);
+    c.e0 = 1.0f / d;
+    c.a1 = __logf(d);
+    c.e02 = c.e0 * c.e0;
+    const float a2 = 0.5f * (1.0f - c.e02);
+    c.pa = c.a1 / (c.a1 + a2);
+    c.ipa = 1.0f / c.pa;
+    c.iqa = 1.0f / (1.0f - c.pa);
+    return c;
+}
+
+__device__ __forceinline__ bool kn_trial(const KN &c, float u1, float u2, float &eps, float &t, float &phu)
+{
+    float e = u1 < c.pa ? __expf(-c.a1 * (u1 * c.ipa)) : sqrtf(fmaf(1.0f - c.e02, (u1 - c.pa) * c.iqa, c.e02));
+    e = fminf(fmaxf(e, c.e0), 1.0f);
+    const float tt = (1.0f - e) * __frcp_rn(c.k * e);
+    const float g = 1.0f - e * (tt * (2.0f - tt)) * __frcp_rn(fmaf(e, e, 1.0f));
+    if (!(u2 < g)) return false;
+    eps = e;
+    t = fminf(tt, 2.0f);
+    phu = fminf(u2 * __frcp_rn(g), 0.99999994f);
+    return true;
+}
+
+// a complete Klein-Nishina sample: trials two per Philox draw until one is accepted
 __device__ __forceinline__ float kn_sample(const Params &P, Part &p, float E, float &t_out, float &phi_u)
 {
-    const float k = E * (1.0f / MEC2F);
-    const float e0 = 1.0f / fmaf(2.0f, k, 1.0f);
-    const float a1 = __logf(fmaf(2.0f, k, 1.0f));
-    const float e02 = e0 * e0;
-    const float a2 = 0.5f * (1.0f - e02);
-    float eps = 1.0f, t = 0.0f;
-    for (int trial = 0; trial < 10000; ++trial) {
+    const KN c = kn_setup(E);
+    float eps = 1.0f, t = 0.0f, phu = 0.5f;
+    for (int draw = 0; draw < 5000; ++draw) {
         const float4 r = rnd4(p, P);
-        eps = (r.x * (a1 + a2) < a1) ? __expf(-a1 * r.y) : sqrtf(fmaf(1.0f - e02, r.y, e02));
-        eps = fminf(fmaxf(eps, e0), 1.0f);
-        t = (1.0f - eps) / (k * eps);
-        const float s2 = t * (2.0f - t);
-        const float g = 1.0f - eps * s2 / fmaf(eps, eps, 1.0f);
-        phi_u = r.w;
-        if (r.z < g) break;
+        if (kn_trial(c, r.x, r.y, eps, t, phu) || kn_trial(c, r.z, r.w, eps, t, phu)) break;
     }
-    t_out = fminf(t, 2.0f);
+    t_out = t;
+    phi_u = phu;
     return eps;
 }
 
@@ -252,52 +279,76 @@ __device__ __forceinline__ float highland(float T, float x, float X0)
 }
 
 // ---------------------------------------------------------------------------------
-// photon interaction at p inside material table `tab` (3 rows of NB_PH) at node n.
-// Returns true while the photon lives.
+// photon interactions.  Each returns true while the photon lives.
 // ---------------------------------------------------------------------------------
-__device__ __forceinline__ bool photon_interact(const Params &P, int region, Part &p, const float *tab, Node n, float rproc,
-                                Local &L, Stages S = Stages{nullptr, nullptr, nullptr})
+// Compton kinematics after a Klein-Nishina sample (eps = E'/E, t = 1 - cos theta, azimuth
+// uniform phu): the photon turns and keeps eps E; the electron takes the rest, in the
+// direction that conserves momentum, on the opposite azimuth.
+__device__ __forceinline__ bool compton_finish(const Params &P, int region, Part &p, float eps, float t, float phu,
+                                               Local &L, Stages S)
 {
-    const float fc = lerp_tab(tab + NB_PH, n), fcp = lerp_tab(tab + 2 * NB_PH, n);
-    p.flags &= ~F_UNSCAT;
     const float E = p.E;
-    if (rproc < fc) {
-        ++L.compton;
-        float t, phu;
-        const float eps = kn_sample(P, p, E, t, phu);
-        const float ct = 1.0f - t, st = sqrtf(fmaxf(0.0f, t * (2.0f - t)));
-        float sp, cp;
-        __sincosf(TWO_PI_F * phu, &sp, &cp);
-        const float Ep = eps * E, T = E - Ep;
-        if (P.diag) ledger(P, p.hist, (double)E - (double)Ep - (double)T);
-        // electron: momentum conservation, opposite azimuth
-        float eu = p.u, ev = p.v, ew = p.w;
-        if (T > 0.0f) {
-            const float pe = sqrtf(T * (T + 2.0f * MEC2F));
-            const float cte = fminf(1.0f, (E - Ep * ct) / pe), ste = fminf(1.0f, Ep * st / pe);
-            rotate(eu, ev, ew, cte, ste, -cp, -sp);
-        }
-        rotate(p.u, p.v, p.w, ct, st, cp, sp);
-        p.E = Ep;
-        emit_electron(P, region, p, T, 1u, eu, ev, ew, L, S);
-        if (Ep < P.pcut) {
-            deposit_point(P, region, p, Ep, L);
-            return false;
-        }
-        return true;
+    const float ct = 1.0f - t, st = sqrtf(fmaxf(0.0f, t * (2.0f - t)));
+    float sp, cp;
+    __sincosf(TWO_PI_F * phu, &sp, &cp);
+    const float Ep = eps * E, T = E - Ep;
+    if (P.diag) ledger(P, p.hist, (double)E - (double)Ep - (double)T);
+    float eu = p.u, ev = p.v, ew = p.w;
+    if (T > 0.0f) {
+        const float pe = sqrtf(T * (T + 2.0f * MEC2F));
+        const float ipe = __frcp_rn(pe);
+        const float cte = fminf(1.0f, (E - Ep * ct) * ipe), ste = fminf(1.0f, Ep * st * ipe);
+        rotate(eu, ev, ew, cte, ste, -cp, -sp);
     }
-    if (rproc < fcp) {
-        ++L.photo;
-        emit_electron(P, region, p, E, 1u, p.u, p.v, p.w, L, S);
+    rotate(p.u, p.v, p.w, ct, st, cp, sp);
+    p.E = Ep;
+    emit_electron(P, region, p, T, 1u, eu, ev, ew, L, S);
+    if (Ep < P.pcut) {
+        deposit_point(P, region, p, Ep, L);
         return false;
     }
+    return true;
+}
+
+// photoelectric absorption: the electron takes the photon's energy and direction
+__device__ __forceinline__ void photo_absorb(const Params &P, int region, Part &p, Local &L, Stages S)
+{
+    ++L.photo;
+    emit_electron(P, region, p, p.E, 1u, p.u, p.v, p.w, L, S);
+}
+
+// pair production: the electron takes a uniform share u of E - 2 m c^2, the positron the rest,
+// both along the photon
+__device__ __forceinline__ void pair_produce(const Params &P, int region, Part &p, float u, Local &L, Stages S)
+{
     ++L.pair;
+    const float E = p.E;
     const float T = E - 2.0f * MEC2F;
-    const float4 r = rnd4(p, P);
-    const float tm = r.x * T, tp = T - tm;
+    const float tm = u * T, tp = T - tm;
     if (P.diag) ledger(P, p.hist, (double)E - (double)tm - (double)tp);
     emit_electron(P, region, p, tm, 1u, p.u, p.v, p.w, L, S);
     emit_electron(P, region, p, tp, 2u, p.u, p.v, p.w, L, S);
+}
+
+// a complete interaction at p inside material table `tab` (3 rows of NB_PH) at node n,
+// with process uniform rproc
+__device__ __forceinline__ bool photon_interact(const Params &P, int region, Part &p, const float *tab, Node n, float rproc,
+                                                Local &L, Stages S = no_stages())
+{
+    const float fc = lerp_tab(tab + NB_PH, n), fcp = lerp_tab(tab + 2 * NB_PH, n);
+    p.flags &= ~F_UNSCAT;
+    if (rproc < fc) {
+        ++L.compton;
+        float t, phu;
+        const float eps = kn_sample(P, p, p.E, t, phu);
+        return compton_finish(P, region, p, eps, t, phu, L, S);
+    }
+    if (rproc < fcp) {
+        photo_absorb(P, region, p, L, S);
+        return false;
+    }
+    const float4 r = rnd4(p, P);
+    pair_produce(P, region, p, r.x, L, S);
     return false;
 }
 
@@ -385,45 +436,38 @@ __global__ __launch_bounds__(WG) void k_source(Params P)
 // photons in the phantom: Woodcock tracking
 // ---------------------------------------------------------------------------------
 template <bool TAB_LDS>
-__global__ __launch_bounds__(WG, 6) void k_photon_phantom(Params P)
+__global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
 {
-    // dynamic LDS: per wave two staging buffers of SSTRIDE words, then the tables when they
-    // are staged
+    // dynamic LDS: per wave two staging buffers (electrons for the phantom queue, photons
+    // for the EPID queue), then the tables when they are staged
     extern __shared__ __align__(16) float lds[];
-    const int wave = threadIdx.x >> 6;
-    constexpr int SWORDS = 2 * SSTRIDE;
-    uint32_t *stage_base = (uint32_t *)lds + (size_t)wave * SWORDS;
+    const int wave = wave_id();
+    constexpr int SWORDS = 2 * stage_words(SBUF);
+    Stages S;
+    stage_carve(S, (uint32_t *)lds + (size_t)wave * SWORDS, (1u << QEP) | (1u << QGE), SBUF);
     float *tabs = lds + (WG / 64) * SWORDS;
     const int ntab = P.nmat_ph * 3 * NB_PH;
     if (TAB_LDS) {
         for (int i = threadIdx.x; i < ntab; i += WG) tabs[i] = P.ph_tab[i];
         for (int i = threadIdx.x; i < NB_PH; i += WG) tabs[ntab + i] = P.ph_maj[i];
     }
-    if (threadIdx.x < 64) {
-        const int w = threadIdx.x >> 4, k = (threadIdx.x >> 3) & 1;
-        if ((threadIdx.x & 7) == 0 && w < WG / 64) ((uint32_t *)lds)[w * SWORDS + k * SSTRIDE + 12 * SBUF] = 0;
-    }
     __syncthreads();
     const float *tab = TAB_LDS ? tabs : P.ph_tab;
     const float *maj = TAB_LDS ? tabs + ntab : P.ph_maj;
-    Stages S;
-    S.e = stage_base;
-    S.g = stage_base + SSTRIDE;
-    S.ee = nullptr;
 
     const uint32_t n = min(P.cnt_in[QGP], P.cap[QGP]);
     Win win{0, 0, 0};
     bool active = false;
+    bool kn = false;   // a Compton collision whose Klein-Nishina sample is still pending
     Part p;
     Local L;
     zero(L);
-    float mubar = 1.0f, mu0 = 0, mu1 = 0, mu2 = 0, mu3 = 0;
+    float imubar = 1.0f, mubar = 1.0f, mu0 = 0, mu1 = 0, mu2 = 0, mu3 = 0;
     Node nd{0, 0.0f};
     float e_cached = -1.0f;
     unsigned long long lane_iters = 0, wave_iters = 0;
     for (;;) {
-        stage_flush(P, S.e, QEP, SBUF / 2);
-        stage_flush(P, S.g, QGE, SBUF / 2);
+        stage_flush_all(P, S, SBUF / 2);
         const bool was = active;
         refill(P, QGP, n, win, active, p);
         const unsigned long long act = __ballot(active);
@@ -432,6 +476,7 @@ __global__ __launch_bounds__(WG, 6) void k_photon_phantom(Params P)
         wave_iters += 64;
         if (active && !was) {
             ++L.items;
+            kn = false;
             if (!in_phantom(P, p.x, p.y, p.z)) {
                 // a source photon whose ray misses the box: EPID or escape
                 place(P, 0, p, L, S);
@@ -443,38 +488,68 @@ __global__ __launch_bounds__(WG, 6) void k_photon_phantom(Params P)
             e_cached = p.E;
             nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
             mubar = lerp_tab(maj, nd);
+            imubar = 1.0f / mubar;
             mu0 = lerp_tab(tab + 0 * 3 * NB_PH, nd);
             if (P.nmat_ph > 1) mu1 = lerp_tab(tab + 1 * 3 * NB_PH, nd);
             if (P.nmat_ph > 2) mu2 = lerp_tab(tab + 2 * 3 * NB_PH, nd);
             if (P.nmat_ph > 3) mu3 = lerp_tab(tab + 3 * 3 * NB_PH, nd);
         }
+        // One Philox draw per lane and iteration, so that every lane of the wave spends its
+        // random-number work together: a flight uses it for the distance, the real/virtual
+        // test, the process and the first Klein-Nishina trial; a pending Compton sample uses
+        // it for two further trials.
         const float4 r = rnd4(p, P);
-        // a flight longer than the box chord leaves the box either way (and an empty
-        // phantom, mubar = 0, must not produce an infinite step)
-        const float s = fminf(-__logf(r.x) / mubar, P.chord);
-        p.x = fmaf(s, p.u, p.x);
-        p.y = fmaf(s, p.v, p.y);
-        p.z = fmaf(s, p.w, p.z);
-        ++L.steps;
-        if (!in_phantom(P, p.x, p.y, p.z)) {
-            // leaves the box on a straight line: EPID or escape
-            place(P, 0, p, L, S);
-            active = false;
-            continue;
+        float eps = 1.0f, t = 0.0f, phu = 0.0f;
+        bool scatter = false;
+        if (kn) {
+            const KN c = kn_setup(p.E);
+            scatter = kn_trial(c, r.x, r.y, eps, t, phu) || kn_trial(c, r.z, r.w, eps, t, phu);
+        } else {
+            // a flight longer than the box chord leaves the box either way (and an empty
+            // phantom, mubar = 0, must not produce an infinite step)
+            const float s = fminf(-__logf(r.x) * imubar, P.chord);
+            p.x = fmaf(s, p.u, p.x);
+            p.y = fmaf(s, p.v, p.y);
+            p.z = fmaf(s, p.w, p.z);
+            ++L.steps;
+            if (!in_phantom(P, p.x, p.y, p.z)) {
+                // leaves the box on a straight line: EPID or escape
+                place(P, 0, p, L, S);
+                active = false;
+                continue;
+            }
+            const int ix = min((int)(p.x * P.idx), P.nx - 1), iy = min((int)(p.y * P.idy), P.ny - 1),
+                      iz = min((int)(p.z * P.idz), P.nz - 1);
+            const uint32_t word = P.vox[((uint32_t)iz * (uint32_t)P.ny + (uint32_t)iy) * (uint32_t)P.nx + (uint32_t)ix];
+            const float rho = __uint_as_float(word & ~3u);
+            const int m = (int)(word & 3u);
+            const float mum = m == 0 ? mu0 : m == 1 ? mu1 : m == 2 ? mu2 : mu3;
+            if (r.y * mubar < rho * mum) {
+                // a real collision: r.z picks the process, and within Compton, rescaled to
+                // (0, 1), it is the first trial's part-and-eps uniform
+                const float *mt = tab + m * 3 * NB_PH;
+                const float fc = lerp_tab(mt + NB_PH, nd);
+                p.flags &= ~F_UNSCAT;
+                if (r.z < fc) {
+                    ++L.compton;
+                    const KN c = kn_setup(p.E);
+                    scatter = kn_trial(c, fminf(r.z * __frcp_rn(fc), 0.99999994f), r.w, eps, t, phu);
+                    kn = !scatter;
+                } else {
+                    const float fcp = lerp_tab(mt + 2 * NB_PH, nd);
+                    if (r.z < fcp) photo_absorb(P, 0, p, L, S);
+                    else pair_produce(P, 0, p, r.w, L, S);
+                    active = false;
+                    continue;
+                }
+            }
         }
-        const int ix = min((int)(p.x * P.idx), P.nx - 1), iy = min((int)(p.y * P.idy), P.ny - 1),
-                  iz = min((int)(p.z * P.idz), P.nz - 1);
-        const uint32_t word = P.vox[((size_t)iz * P.ny + iy) * P.nx + ix];
-        const float rho = __uint_as_float(word & ~3u);
-        const int m = (int)(word & 3u);
-        const float mum = m == 0 ? mu0 : m == 1 ? mu1 : m == 2 ? mu2 : mu3;
-        if (r.y * mubar < rho * mum) {
-            active = photon_interact(P, 0, p, tab + m * 3 * NB_PH, nd, r.z, L, S);
-            if (!active) e_cached = -1.0f;
+        if (scatter) {
+            kn = false;
+            active = compton_finish(P, 0, p, eps, t, phu, L, S);
         }
     }
-    stage_flush(P, S.e, QEP, 1);
-    stage_flush(P, S.g, QGE, 1);
+    stage_flush_all(P, S, 1);
     flush_stats(P, L, S_WOODCOCK, QGP, lane_iters, wave_iters);
 }
 
@@ -486,19 +561,15 @@ template __global__ void k_photon_phantom<false>(Params);
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
 {
-    // dynamic LDS: the layer tables, then per wave one staging buffer (SSTRIDE words) for the
-    // electrons set in motion in the EPID
+    // dynamic LDS: the layer tables, then per wave one staging buffer for the electrons set
+    // in motion in the EPID
     extern __shared__ __align__(16) float lds[];
     __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS];
     const int ntab = P.nl * 3 * NB_PH;
     const float *src = P.ph_tab + MAX_PMAT * 3 * NB_PH;
     for (int i = threadIdx.x; i < ntab; i += WG) lds[i] = src[i];
-    uint32_t *stage = (uint32_t *)(lds + ntab) + (threadIdx.x >> 6) * SSTRIDE;
-    if ((threadIdx.x & 63) == 0) stage[12 * SBUF] = 0;
     Stages S;
-    S.e = nullptr;
-    S.g = nullptr;
-    S.ee = stage;
+    stage_carve(S, (uint32_t *)(lds + ntab) + wave_id() * stage_words(SBUF), 1u << QEE, SBUF);
     if (threadIdx.x <= MAX_LAYERS) s_zl[threadIdx.x] = P.zl[threadIdx.x];
     if (threadIdx.x < MAX_LAYERS) s_rho[threadIdx.x] = P.lrho[threadIdx.x];
     __syncthreads();
@@ -511,7 +582,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
     zero(L);
     unsigned long long lane_iters = 0, wave_iters = 0;
     for (;;) {
-        stage_flush(P, S.ee, QEE, SBUF / 2);
+        stage_flush_all(P, S, SBUF / 2);
         const bool was = active;
         refill(P, QGE, n, win, active, p);
         const unsigned long long act = __ballot(active);
@@ -562,7 +633,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
         p.z = dl > 0 ? s_zl[l + 1] : s_zl[l];
         p.flags = (p.flags & ~F_LAYER_MASK) | ((uint32_t)nlay << F_LAYER_SHIFT);
     }
-    stage_flush(P, S.ee, QEE, 1);
+    stage_flush_all(P, S, 1);
     flush_stats(P, L, S_EPID_PH_STEPS, QGE, lane_iters, wave_iters);
 }
 
@@ -577,6 +648,11 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
     const int nm = EPID ? P.nl : P.nmat_ph;
     const float *src = P.el_tab + (EPID ? MAX_PMAT : 0) * 3 * NB_EL;
     for (int i = threadIdx.x; i < nm * 3 * NB_EL; i += WG) lds[i] = src[i];
+    // after the tables, per wave staging buffers for every kind this kernel appends to
+    const unsigned smask = EPID ? (1u << QGE) | (1u << QEE) : (1u << QGP) | (1u << QEP) | (1u << QGE) | (1u << QEE);
+    constexpr int nstage = EPID ? 2 : 4;
+    Stages S;
+    stage_carve(S, (uint32_t *)(lds + nm * 3 * NB_EL) + wave_id() * nstage * stage_words(SBUF_E), smask, SBUF_E);
     if (threadIdx.x <= MAX_LAYERS) s_zl[threadIdx.x] = P.zl[threadIdx.x];
     if (threadIdx.x < MAX_LAYERS) {
         s_rho[threadIdx.x] = P.lrho[threadIdx.x];
@@ -600,6 +676,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
     int nsteps = 0;
     unsigned long long lane_iters = 0, wave_iters = 0;
     for (;;) {
+        stage_flush_all(P, S, SBUF_E / 2);
         const bool was = active;
         refill(P, kind, n, win, active, p);
         const unsigned long long act = __ballot(active);
@@ -733,7 +810,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                     if (P.diag) ledger(P, p.hist, (double)T - (double)Tp - (double)W);
                     T = Tp;
                     p.E = T;
-                    emit_electron(P, region, p, W, 1u, du, dv, dw, L);
+                    emit_electron(P, region, p, W, 1u, du, dv, dw, L, S);
                 } else {
                     ++L.brems;
                     const float k = (float)KCUT * __expf(r2.y * __logf(T * (float)(1.0 / KCUT)));
@@ -741,14 +818,14 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                     if (P.diag) ledger(P, p.hist, (double)T - (double)Tn - (double)k);
                     T = Tn;
                     p.E = T;
-                    emit_photon(P, region, p, k, p.u, p.v, p.w, L);
+                    emit_photon(P, region, p, k, p.u, p.v, p.w, L, S);
                 }
             }
         }
         p.x = (float)px; p.y = (float)py; p.z = (float)pz;
         if (T < P.ecut) {
             deposit_point(P, region, p, T, L);
-            if ((p.flags & F_TYPE) == 2u) annihilate(P, region, p, L);
+            if ((p.flags & F_TYPE) == 2u) annihilate(P, region, p, L, S);
             active = false;
             continue;
         }
@@ -761,7 +838,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                 if (r == 0) {
                     px = p.x; py = p.y; pz = p.z;   // re-entered through a face
                 } else {
-                    if (r == 1) qappend(P, QEE, true, p);
+                    if (r == 1) append(P, S, QEE, true, p);
                     else ledger(P, p.hist, (double)p.E);
                     active = false;
                 }
@@ -775,6 +852,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
             }
         }
     }
+    stage_flush_all(P, S, 1);
     flush_stats(P, L, EPID ? S_ESTEP_E : S_ESTEP_P, kind, lane_iters, wave_iters);
 }
 
@@ -970,9 +1048,10 @@ __global__ void k_dbg_sample(Params P, int kind, float p0, float p1, float p2, f
     Part p;
     p.hist = (uint32_t)i; p.plo = 0x5A5Au; p.phi = (uint32_t)kind; p.draw = 0; p.flags = 0;
     float phu;
-    if (kind == 0) {
+    if (kind == 0 || kind == 5) {
         float t;
-        out[i] = kn_sample(P, p, p0, t, phu);
+        const float eps = kn_sample(P, p, p0, t, phu);
+        out[i] = kind == 0 ? eps : phu;
     } else if (kind == 1) {
         out[i] = moller_sample(P, p, p0, phu);
     } else if (kind == 2) {
@@ -1061,10 +1140,10 @@ hipError_t launch_source(const Params &P, hipStream_t s)
 size_t lds_bytes(int kind, const Params &P)
 {
     switch (kind) {
-    case QGP: return (size_t)(WG / 64) * 2 * SSTRIDE * 4 + (PH_TAB_LDS ? (size_t)(P.nmat_ph * 3 + 1) * NB_PH * 4 : 0);
-    case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float) + (size_t)(WG / 64) * SSTRIDE * 4;
-    case QEP: return (size_t)P.nmat_ph * 3 * NB_EL * sizeof(float);
-    default: return (size_t)P.nl * 3 * NB_EL * sizeof(float);
+    case QGP: return (size_t)(WG / 64) * 2 * stage_words(SBUF) * 4 + (PH_TAB_LDS ? (size_t)(P.nmat_ph * 3 + 1) * NB_PH * 4 : 0);
+    case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float) + (size_t)(WG / 64) * stage_words(SBUF) * 4;
+    case QEP: return (size_t)P.nmat_ph * 3 * NB_EL * sizeof(float) + (size_t)(WG / 64) * 4 * stage_words(SBUF_E) * 4;
+    default: return (size_t)P.nl * 3 * NB_EL * sizeof(float) + (size_t)(WG / 64) * 2 * stage_words(SBUF_E) * 4;
     }
 }
 

@@ -72,6 +72,24 @@ def test_device_kn_sampler(E, En):
     assert chi2_p(obs, exp) > 1e-4
 
 
+@pytest.mark.parametrize("En", [0.1, 2.0])
+def test_device_kn_azimuth_uniform_and_independent(E, En):
+    """The azimuth comes from the accepted trial's acceptance variate rescaled by the
+    rejection function: it must be uniform on (0, 1) and independent of the scattering
+    angle (kinds 0 and 5 replay the same streams, so sample i of both is one interaction)."""
+    eng = E.Engine(0, seed=11)
+    n = 400_000
+    eps = eng.debug_sample(0, n, En).astype(np.float64)
+    phu = eng.debug_sample(5, n, En).astype(np.float64)
+    assert phu.min() > 0.0 and phu.max() < 1.0
+    assert stats.kstest(phu, "uniform").pvalue > 1e-3
+    med = np.median(eps)
+    for part in (phu[eps < med], phu[eps >= med]):
+        assert stats.kstest(part, "uniform").pvalue > 1e-3
+    # no linear dependence either
+    assert abs(np.corrcoef(eps, phu)[0, 1]) < 5.0 / math.sqrt(n)
+
+
 def moller_dens(T, W):
     g = T / MEC2 + 1
     Tp = T - W
