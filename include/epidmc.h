@@ -29,8 +29,8 @@
  *
  * Errors: every call returns an epidmc_status; no exception crosses the ABI.
  * epidmc_last_error() returns a message for the last failed call on a context.
- * Device-side faults (queue overflow, step-limit, NaN energy, fixed-point
- * overflow) are latched in a device error word and reported as
+ * Device-side faults (queue overflow, step limit, sampler draw limit, NaN
+ * energy, fixed-point overflow) are latched in a device error word and reported as
  * EPIDMC_E_OVERFLOW / EPIDMC_E_NAN by the next call that synchronises (run,
  * run_until, get_counters).  A context is not thread safe; use one per thread.
  */
@@ -53,7 +53,7 @@ typedef enum {
     EPIDMC_E_NOT_READY = -4,  /* model incomplete or workspace not bound */
     EPIDMC_E_WORKSPACE = -5,  /* workspace too small or misaligned */
     EPIDMC_E_DEVICE = -6,     /* HIP runtime error */
-    EPIDMC_E_OVERFLOW = -7,   /* particle queue, step limit or fixed-point overflow */
+    EPIDMC_E_OVERFLOW = -7,   /* particle queue, step limit, sampler draw limit or fixed-point overflow */
     EPIDMC_E_NAN = -8         /* non-finite energy or position met on the device */
 } epidmc_status;
 

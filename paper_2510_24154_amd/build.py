@@ -8,8 +8,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libepidmc.so")
 SOURCES = ["epidmc.cpp", "tables.cpp", "kernels.hip"]
+# FP32 division and square root at the hardware's 1-2.5 ulp instead of correctly rounded
+# sequences, and FP32 denormals flushed: no FP32 quantity of the transport comes near the
+# denormal range, and the tallies and positions that need more than FP32 are FP64
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero",
          "-Wall", "-Wno-unused-function"]
 
 

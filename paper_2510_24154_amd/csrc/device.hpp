@@ -41,7 +41,13 @@ struct Part {
 
 __device__ __forceinline__ float4 rnd4(Part &p, const Params &P)
 {
-    const uint4 r = philox10(p.draw++, p.plo, p.phi, p.hist, P.key0, P.key1);
+    // the key is a wave-uniform value; hiding it from the optimiser at each call keeps the
+    // compiler from hoisting the ten-round key schedule (twenty scalar registers) out of the
+    // transport loops, where it would push other uniforms into spill slots: the schedule is
+    // recomputed with scalar adds, which issue beside the vector work
+    uint32_t k0 = P.key0, k1 = P.key1;
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    const uint4 r = philox10(p.draw++, p.plo, p.phi, p.hist, k0, k1);
     return make_float4(u01(r.x), u01(r.y), u01(r.z), u01(r.w));
 }
 
@@ -91,23 +97,42 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 // the wave's index in its workgroup, as a scalar (wave-uniform) value
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
-// Append to the next-iteration queue of `kind`: the lanes currently executing that have
-// `pred` set take consecutive slots with a single atomic per wave.  Valid in divergent
-// code: the ballot only sees the executing lanes and the leader is one of them.
-__device__ __forceinline__ void qappend(const Params &P, int kind, bool pred, const Part &p)
+// segment counters: [kind][segment], one 128-byte line each
+__device__ __forceinline__ uint32_t *seg_ctr(uint32_t *base, int kind, uint32_t s)
 {
-    const unsigned long long m = __ballot(pred);
-    if (m == 0) return;
-    const int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0;
-    if ((int)lane_id() == leader)
-        base = atomicAdd(&P.cnt_out[kind], (uint32_t)__popcll(m));
-    base = __shfl(base, leader);
-    if (pred) {
-        const uint32_t i = base + (uint32_t)__popcll(m & __lanemask_lt());
-        if (i < P.cap[kind]) qstore(P.out[kind], i, p);
-        else atomicOr(P.err, ERR_QUEUE);
+    return base + ((uint32_t)kind * NSEG + s) * CSTRIDE;
+}
+
+// A wave's home segment.  Workgroups are dealt to the XCDs in turn, so with WG / 64 = 4 waves
+// per workgroup and NSEG = 64 every segment is used by the waves of a single XCD.
+__device__ __forceinline__ uint32_t home_seg() { return ((uint32_t)blockIdx.x * (WG / 64) + (uint32_t)wave_id()) % NSEG; }
+
+// Append to the next-pass queue of `kind`: the executing lanes with `pred` set take
+// consecutive slots of segment `seg`, one atomic per wave; lanes that find the segment full
+// move on to the next segment.  Valid in divergent code: the ballot only sees the executing
+// lanes and the leader is one of them.  A particle that finds every segment full is dropped
+// and the overflow is latched in the error word.
+__device__ __forceinline__ void qappend(const Params &P, int kind, bool pred, const Part &p, uint32_t seg)
+{
+    bool pending = pred;
+    const uint32_t cap = P.segcap[kind];
+    for (int tries = 0; tries < NSEG; ++tries) {
+        const unsigned long long m = __ballot(pending);
+        if (m == 0) return;
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if ((int)lane_id() == leader) base = atomicAdd(seg_ctr(P.cnt_out, kind, seg), (uint32_t)__popcll(m));
+        base = __shfl(base, leader);
+        if (pending) {
+            const uint32_t i = base + (uint32_t)__popcll(m & __lanemask_lt());
+            if (i < cap) {
+                qstore(P.out[kind], seg * cap + i, p);
+                pending = false;
+            }
+        }
+        seg = (seg + 1) % NSEG;
     }
+    if (pending) atomicOr(P.err, ERR_QUEUE);
 }
 
 // ---------------------------------------------------------------------------------
@@ -121,11 +146,12 @@ __device__ __forceinline__ void qappend(const Params &P, int kind, bool pred, co
 struct Stages {
     uint32_t *w[NQ];
     uint32_t sb;
+    uint32_t seg;   // the segment the wave's flushes go to (advances when it fills)
 };
 
 __host__ __device__ constexpr int stage_words(int sb) { return 12 * sb + 4; }
 
-__device__ __forceinline__ Stages no_stages() { return Stages{{nullptr, nullptr, nullptr, nullptr}, 0}; }
+__device__ __forceinline__ Stages no_stages() { return Stages{{nullptr, nullptr, nullptr, nullptr}, 0, 0}; }
 
 __device__ __forceinline__ void stage_put(uint32_t *w, uint32_t sb, uint32_t i, const Part &p)
 {
@@ -150,18 +176,14 @@ __device__ __forceinline__ void append(const Params &P, const Stages &S, int kin
 {
     uint32_t *w = S.w[kind];
     if (!w) {
-        qappend(P, kind, pred, p);
+        qappend(P, kind, pred, p, home_seg());
         return;
     }
     if (!pred) return;
     const uint32_t i = __hip_atomic_fetch_add(w + 12 * S.sb, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    if (i < S.sb) {
-        stage_put(w, S.sb, i, p);
-    } else {
-        const uint32_t g = atomicAdd(&P.cnt_out[kind], 1u);
-        if (g < P.cap[kind]) qstore(P.out[kind], g, p);
-        else atomicOr(P.err, ERR_QUEUE);
-    }
+    const bool full = i >= S.sb;
+    if (!full) stage_put(w, S.sb, i, p);
+    if (__ballot(full)) qappend(P, kind, full, p, home_seg());
 }
 
 // move a wave's staged particles of `kind` to the global queue when at least `minfill` are
@@ -170,7 +192,7 @@ __device__ __forceinline__ void append(const Params &P, const Stages &S, int kin
 // fill count is read and reset with wave-scope atomics, and wave barriers keep the compiler
 // from moving the staged reads and writes across them (a fence would also wait for every
 // outstanding global load and store of the wave).
-__device__ __forceinline__ void stage_flush(const Params &P, const Stages &S, int kind, uint32_t minfill)
+__device__ __forceinline__ void stage_flush(const Params &P, Stages &S, int kind, uint32_t minfill)
 {
     uint32_t *w = S.w[kind];
     if (!w) return;
@@ -178,20 +200,26 @@ __device__ __forceinline__ void stage_flush(const Params &P, const Stages &S, in
     const uint32_t n =
         min(__hip_atomic_load(w + 12 * S.sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT), S.sb);
     if (n == 0 || n < minfill) return;
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(&P.cnt_out[kind], n);
-    base = __shfl(base, 0);
-    for (uint32_t i = lane_id(); i < n; i += 64) {
-        if (base + i < P.cap[kind]) stage_copy(P.out[kind], base + i, w, S.sb, i);
-        else atomicOr(P.err, ERR_QUEUE);
+    // reserve in the wave's current segment; what does not fit goes to the next one
+    const uint32_t cap = P.segcap[kind];
+    uint32_t done = 0;
+    for (int tries = 0; tries < NSEG && done < n; ++tries) {
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(seg_ctr(P.cnt_out, kind, S.seg), n - done);
+        base = __shfl(base, 0);
+        const uint32_t fit = base < cap ? min(n - done, cap - base) : 0u;
+        for (uint32_t i = lane_id(); i < fit; i += 64) stage_copy(P.out[kind], S.seg * cap + base + i, w, S.sb, done + i);
+        done += fit;
+        if (done < n) S.seg = (S.seg + 1) % NSEG;
     }
+    if (done < n && lane_id() == 0) atomicOr(P.err, ERR_QUEUE);
     __builtin_amdgcn_wave_barrier();
     if (lane_id() == 0) __hip_atomic_store(w + 12 * S.sb, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     __builtin_amdgcn_wave_barrier();
 }
 
 // flush every staged kind (at least `minfill` waiting); wave converged
-__device__ __forceinline__ void stage_flush_all(const Params &P, const Stages &S, uint32_t minfill)
+__device__ __forceinline__ void stage_flush_all(const Params &P, Stages &S, uint32_t minfill)
 {
 #pragma unroll
     for (int k = 0; k < NQ; ++k) stage_flush(P, S, k, minfill);
@@ -203,6 +231,7 @@ __device__ __forceinline__ int stage_carve(Stages &S, uint32_t *base, unsigned m
 {
     S = no_stages();
     S.sb = sb;
+    S.seg = home_seg();
     int used = 0;
 #pragma unroll
     for (int k = 0; k < NQ; ++k)
@@ -214,30 +243,51 @@ __device__ __forceinline__ int stage_carve(Stages &S, uint32_t *base, unsigned m
     return used;
 }
 
-// Wave-uniform window of queue items claimed WIN at a time.
+// Wave-uniform window [b, e) of queue items (absolute indices) claimed WIN at a time from
+// segment `seg`; a wave starts at its home segment and moves through the others as they
+// run dry, so the waves share the work to the end with claims spread over NSEG counters.
 struct Win {
-    uint32_t b, e;
+    uint32_t b, e, seg, tried;
     int done;
 };
 
+__device__ __forceinline__ Win win_start() { return Win{0u, 0u, home_seg(), 0u, 0}; }
+
 constexpr uint32_t NO_ITEM = 0xFFFFFFFFu;
 
+// next window of queue `kind`, or done
+__device__ __forceinline__ void next_window(const Params &P, int kind, Win &win)
+{
+    const uint32_t cap = P.segcap[kind];
+    while (!win.done) {
+        const uint32_t ns = min((uint32_t)__builtin_amdgcn_readfirstlane(*seg_ctr(P.cnt_in, kind, win.seg)), cap);
+        uint32_t *head = seg_ctr(P.heads, kind, win.seg);
+        // a plain read first: an exhausted segment costs no atomic
+        uint32_t b = __builtin_amdgcn_readfirstlane(__hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (b < ns) {
+            if (lane_id() == 0) b = atomicAdd(head, (uint32_t)WIN);
+            b = __shfl(b, 0);
+        }
+        if (b < ns) {
+            win.b = win.seg * cap + b;
+            win.e = win.seg * cap + min(b + (uint32_t)WIN, ns);
+            return;
+        }
+        if (++win.tried == NSEG) win.done = 1;
+        else win.seg = (win.seg + 1) % NSEG;
+    }
+}
+
 // Give the lanes of a converged wave that `want` an item consecutive unclaimed items of
-// queue `kind` (of n), claimed from the global head WIN at a time; returns this lane's
-// item or NO_ITEM when the queue is exhausted.
-__device__ __forceinline__ uint32_t claim(const Params &P, int kind, uint32_t n, Win &win, bool want)
+// queue `kind`; returns this lane's item or NO_ITEM when the queue is exhausted.
+__device__ __forceinline__ uint32_t claim(const Params &P, int kind, Win &win, bool want)
 {
     uint32_t item = NO_ITEM;
     unsigned long long need = __ballot(want);
     while (need) {
         if (win.b >= win.e) {
+            next_window(P, kind, win);
             if (win.done) break;
-            uint32_t b = 0;
-            if (lane_id() == 0) b = atomicAdd(&P.heads[kind], (uint32_t)WIN);
-            b = __shfl(b, 0);
-            if (b >= n) { win.done = 1; break; }
-            win.b = b;
-            win.e = min(b + (uint32_t)WIN, n);
         }
         const uint32_t avail = win.e - win.b;
         const uint32_t rank = (uint32_t)__popcll(need & __lanemask_lt());
@@ -249,9 +299,9 @@ __device__ __forceinline__ uint32_t claim(const Params &P, int kind, uint32_t n,
 }
 
 // Give every idle lane of a converged wave the next unclaimed particle of queue `kind`.
-__device__ __forceinline__ void refill(const Params &P, int kind, uint32_t n, Win &win, bool &active, Part &p)
+__device__ __forceinline__ void refill(const Params &P, int kind, Win &win, bool &active, Part &p)
 {
-    const uint32_t i = claim(P, kind, n, win, !active);
+    const uint32_t i = claim(P, kind, win, !active);
     if (i != NO_ITEM) {
         p = qload(P.in[kind], i);
         active = true;
@@ -301,7 +351,7 @@ __device__ __forceinline__ void rotate(float &u, float &v, float &w, float ct, f
     const float s2 = fmaf(-w, w, 1.0f);
     float nu, nv, nw;
     if (s2 > 1e-10f) {
-        const float s = sqrtf(s2), is = 1.0f / s;
+        const float is = rsqrtf(s2), s = s2 * is;
         nu = u * ct + st * (u * w * cp - v * sp) * is;
         nv = v * ct + st * (v * w * cp + u * sp) * is;
         nw = w * ct - st * cp * s;

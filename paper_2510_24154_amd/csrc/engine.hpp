@@ -18,6 +18,8 @@ constexpr int WG = 256;            // threads per workgroup of the transport ker
 constexpr int WIN = 128;           // queue items a wave claims per atomic
 constexpr int SBUF = 64;           // particles a wave stages in LDS per queue kind before one bulk append
 constexpr int SBUF_E = 16;         // the same for the electron kernels, whose appends are rarer
+constexpr int NSEG = 64;           // segments per queue, each with its own fill counter and consume head
+constexpr int CSTRIDE = 32;        // u32 words from one segment counter to the next (one 128-byte line each)
 constexpr int ITEMS_PER_LANE = 8;  // a pass launches enough waves for about this many items per lane:
                                    // a wave lives as long as its slowest particle, so thinner waves waste lanes
 
@@ -32,7 +34,8 @@ constexpr uint32_t F_LAYER_MASK = 7u << F_LAYER_SHIFT;
 constexpr uint32_t F_SLOT_SHIFT = 8;     // variance batch slot (8 bits)
 
 // device error word bits
-constexpr uint32_t ERR_QUEUE = 1u, ERR_STEPS = 2u, ERR_NAN = 4u, ERR_FIXED = 8u;
+constexpr uint32_t ERR_QUEUE = 1u, ERR_STEPS = 2u, ERR_NAN = 4u, ERR_FIXED = 8u, ERR_SAMPLE = 16u;
+constexpr int MAX_KN_ROUNDS = 1000;  // Klein-Nishina draws of one pending sample (acceptance is at least 1/2 per trial)
 
 // model constants of the physics readings (shared meaning with the documentation;
 // the numbers are typed here once for the engine)
@@ -60,10 +63,14 @@ struct Queue {
 struct Params {
     // queues of this pass: `in` is consumed, `out` is appended to (the host swaps the two
     // buffer sets between passes, so kernels never index them at run time)
+    // A queue is NSEG segments of segcap particles; segment s holds items [s segcap, (s+1) segcap).
+    // Its fill counter and consume head sit on their own cache lines ([kind][s] x CSTRIDE), so
+    // the appends and claims of different waves spread over many addresses instead of
+    // serialising on one.
     Queue in[NQ], out[NQ];
-    uint32_t cap[NQ];
-    uint32_t *cnt;             // [2][NQ] fill counters, then [NQ] consume heads, record count
-    uint32_t *cnt_in, *cnt_out, *heads;
+    uint32_t segcap[NQ];
+    uint32_t *cnt;             // [0, NQ): particles per queue after a pass (summed segments); [3 NQ]: record count
+    uint32_t *cnt_in, *cnt_out, *heads;   // segment fill counters being consumed / appended to, consume heads
     uint32_t *err;             // error word
     unsigned long long *stats; // work counters (see Stat)
 
@@ -91,6 +98,9 @@ struct Params {
     // tables (global memory copies, staged to LDS by the kernels)
     const float *ph_tab;        // [MAX_PMAT + MAX_LAYERS][3][NB_PH]: mu/rho, f_compton, f_compton+photo
     const float *ph_maj;        // [NB_PH] phantom majorant, 1/cm
+    const float4 *ph_mu4;       // [NB_PH] mu/rho of the four phantom material slots (0 when unused)
+    const float2 *ph_fr;        // [MAX_PMAT][NB_PH] f_compton, f_compton+photo
+    float rmaj[MAX_PMAT];       // largest density of each phantom slot x (1 + 1e-5)
     const float *el_tab;        // [MAX_PMAT + MAX_LAYERS][3][NB_EL]: range, sigma_hard, f_moller
     float ph_lnE0, ph_idl;      // photon grid: ln E0 and 1/d(lnE)
     float el_lnT0, el_idl;      // electron grid

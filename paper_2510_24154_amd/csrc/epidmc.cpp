@@ -25,6 +25,7 @@ hipError_t launch_image(const Params &P, double n, double nb, double *mean, doub
 hipError_t launch_sigma_bar(const Params &P, double n, double nb, double thr, double *out, hipStream_t s);
 hipError_t launch_diag_check(const Params &P, uint32_t nh, unsigned long long *maxbits, double *sums, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_seg_total(const Params &P, const uint32_t *cnt, uint32_t *tot, hipStream_t s);
 hipError_t launch_dbg_philox(const Params &P, const uint32_t *ctr, uint32_t *out, unsigned long long n, hipStream_t s);
 hipError_t launch_dbg_sample(const Params &P, int kind, float p0, float p1, float p2, float *out,
                              unsigned long long n, hipStream_t s);
@@ -41,16 +42,18 @@ struct Region {
 };
 
 struct Layout {
-    Region vox, ph_tab, ph_maj, el_tab, sp_lo, sp_hi, sp_prob, sp_alias, ap_a, ap_b, ap_prob, ap_alias, seg_end,
-        phsp, ctl, queues, img, sum, sum2, led, ein, rec_pix, rec_e, k_count, k_cursor, k_bsum, k_sorted;
+    Region vox, ph_tab, ph_maj, ph_mu4, ph_fr, el_tab, sp_lo, sp_hi, sp_prob, sp_alias, ap_a, ap_b, ap_prob, ap_alias, seg_end,
+        phsp, ctl, segc, queues, img, sum, sum2, led, ein, rec_pix, rec_e, k_count, k_cursor, k_bsum, k_sorted;
     size_t total;
-    uint32_t cap[NQ];
+    uint32_t cap[NQ];          // particles per queue: NSEG segments of segcap
+    uint32_t segcap[NQ];
     uint32_t rec_cap;
     int ring;
     uint64_t chunk;
 };
 
-constexpr size_t CTL_CNT = 0;                 // 16 u32: [2][NQ] counts, [NQ] heads, record count
+constexpr size_t CTL_CNT = 0;                 // 16 u32: [NQ] particles per queue after a pass, [3 NQ] record count
+constexpr size_t SEG_SET = (size_t)NQ * NSEG * CSTRIDE;   // u32 words of one set of segment counters
 constexpr size_t CTL_ERR = 64;                // u32
 constexpr size_t CTL_STATS = 128;             // S_NSTAT u64
 constexpr size_t CTL_DIAG = CTL_STATS + 8 * 32;   // max-residual bits, e_in, e_ledger
@@ -461,6 +464,10 @@ static Layout make_layout(const epidmc_ctx *c)
     L.cap[QEP] = (uint32_t)(4 * H + 4096);
     L.cap[QGE] = (uint32_t)(2 * H + 4096);
     L.cap[QEE] = (uint32_t)(2 * H + 4096);
+    for (int k = 0; k < NQ; ++k) {
+        L.segcap[k] = (L.cap[k] + NSEG - 1) / NSEG;
+        L.cap[k] = L.segcap[k] * NSEG;
+    }
     L.rec_cap = c->tally_mode == 2 ? (uint32_t)(8 * H + 4096) : 0;
     L.ring = std::min(c->batches, MAX_SLOTS);
     const int nbins = std::max<int>(1, (int)c->weights.size());
@@ -468,6 +475,8 @@ static Layout make_layout(const epidmc_ctx *c)
     take(L.vox, nvox * 4);
     take(L.ph_tab, (size_t)(MAX_PMAT + MAX_LAYERS) * 3 * NB_PH * 4);
     take(L.ph_maj, NB_PH * 4);
+    take(L.ph_mu4, NB_PH * 16);
+    take(L.ph_fr, (size_t)MAX_PMAT * NB_PH * 8);
     take(L.el_tab, (size_t)(MAX_PMAT + MAX_LAYERS) * 3 * NB_EL * 4);
     take(L.sp_lo, nbins * 4);
     take(L.sp_hi, nbins * 4);
@@ -480,6 +489,7 @@ static Layout make_layout(const epidmc_ctx *c)
     take(L.seg_end, (size_t)std::max(1, c->n_seg) * 8);
     take(L.phsp, std::max<size_t>(1, c->n_phsp) * 32);
     take(L.ctl, CTL_BYTES);
+    take(L.segc, 3 * SEG_SET * 4);   // segment fill counters of the two buffer sets, consume heads
     size_t qb = 0;
     for (int k = 0; k < NQ; ++k) qb += (size_t)L.cap[k] * 48;
     take(L.queues, 2 * qb);
@@ -568,6 +578,16 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
         for (int s2 = 0; s2 < nslot; ++s2) m = std::max(m, (double)rho_max[s2] * ph_tab[(size_t)s2 * 3 * NB_PH + i]);
         maj[i] = (float)(m * (1.0 + 1e-5));   // margin over the FP32 rounding of rho * mu
     }
+    // the Woodcock kernel's packed copies: per node the four slots' mu/rho in one 16-byte word,
+    // per slot and node the two cumulative process fractions in one 8-byte word
+    std::vector<float> mu4((size_t)NB_PH * 4, 0.0f), fr((size_t)MAX_PMAT * NB_PH * 2, 0.0f);
+    for (int s2 = 0; s2 < nslot; ++s2)
+        for (int i = 0; i < NB_PH; ++i) {
+            const float *t = &ph_tab[(size_t)s2 * 3 * NB_PH];
+            mu4[(size_t)i * 4 + s2] = t[i];
+            fr[((size_t)s2 * NB_PH + i) * 2] = t[NB_PH + i];
+            fr[((size_t)s2 * NB_PH + i) * 2 + 1] = t[2 * NB_PH + i];
+        }
 
     // source
     const int nbins = std::max<int>(1, (int)c->weights.size());
@@ -609,6 +629,8 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
     HIPCHK(up(L.vox, vox.data(), nvox * 4));
     HIPCHK(up(L.ph_tab, ph_tab.data(), ph_tab.size() * 4));
     HIPCHK(up(L.ph_maj, maj.data(), maj.size() * 4));
+    HIPCHK(up(L.ph_mu4, mu4.data(), mu4.size() * 4));
+    HIPCHK(up(L.ph_fr, fr.data(), fr.size() * 4));
     HIPCHK(up(L.el_tab, el_tab.data(), el_tab.size() * 4));
     HIPCHK(up(L.sp_lo, sp_lo.data(), nbins * 4));
     HIPCHK(up(L.sp_hi, sp_hi.data(), nbins * 4));
@@ -638,10 +660,10 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
             uint4 **fp[3] = {&Q.a, &Q.b, &Q.c};
             for (int f = 0; f < 3; ++f) { *fp[f] = (uint4 *)q; q += n * 16; }
         }
-    for (int k = 0; k < NQ; ++k) P.cap[k] = L.cap[k];
+    for (int k = 0; k < NQ; ++k) P.segcap[k] = L.segcap[k];
     char *ctl = w + L.ctl.off;
     P.cnt = (uint32_t *)(ctl + CTL_CNT);
-    P.heads = P.cnt + 2 * NQ;
+    P.heads = nullptr;   // set per pass by run_chunk (segment counters)
     P.err = (uint32_t *)(ctl + CTL_ERR);
     P.stats = (unsigned long long *)(ctl + CTL_STATS);
     P.nx = c->nx; P.ny = c->ny; P.nz = c->nz;
@@ -678,6 +700,9 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
     P.ph_to_epid_z = (float)((double)c->front_z - (double)c->origin[2]);
     P.ph_tab = (const float *)(w + L.ph_tab.off);
     P.ph_maj = (const float *)(w + L.ph_maj.off);
+    P.ph_mu4 = (const float4 *)(w + L.ph_mu4.off);
+    P.ph_fr = (const float2 *)(w + L.ph_fr.off);
+    for (int s2 = 0; s2 < MAX_PMAT; ++s2) P.rmaj[s2] = (float)((double)rho_max[s2] * (1.0 + 1e-5));
     P.el_tab = (const float *)(w + L.el_tab.off);
     P.ph_lnE0 = (float)ph0; P.ph_idl = (float)(1.0 / phd);
     P.el_lnT0 = (float)el0; P.el_idl = (float)(1.0 / eld);
@@ -747,6 +772,7 @@ static epidmc_status check_error_word(epidmc_ctx *c, uint32_t e)
     if (e & ERR_QUEUE) return fail(c, EPIDMC_E_OVERFLOW, "particle queue overflow: lower max_chunk_histories");
     if (e & ERR_STEPS) return fail(c, EPIDMC_E_OVERFLOW, "electron step limit exceeded");
     if (e & ERR_FIXED) return fail(c, EPIDMC_E_OVERFLOW, "fixed-point tally overflow");
+    if (e & ERR_SAMPLE) return fail(c, EPIDMC_E_OVERFLOW, "Klein-Nishina sample not accepted within the draw limit");
     return EPIDMC_OK;
 }
 
@@ -763,12 +789,15 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
     P.h0 = h0;
     P.h1 = h1;
     uint32_t *cnt = P.cnt;
+    uint32_t *seg = (uint32_t *)(c->ws + c->lay.segc.off);   // [set A, set B, heads][NQ][NSEG] x CSTRIDE
     HIPCHK(launch_zero(cnt, 64, s));
-    // the source appends into buffer 0
+    HIPCHK(launch_zero(seg, 3 * SEG_SET * 4, s));
+    // the source appends into buffer set 0
     auto use = [&](int cur) {
         for (int k = 0; k < NQ; ++k) { P.in[k] = c->qs[cur][k]; P.out[k] = c->qs[1 - cur][k]; }
-        P.cnt_in = cnt + cur * NQ;
-        P.cnt_out = cnt + (1 - cur) * NQ;
+        P.cnt_in = seg + cur * SEG_SET;
+        P.cnt_out = seg + (1 - cur) * SEG_SET;
+        P.heads = seg + 2 * SEG_SET;
     };
     use(1);
     HIPCHK(launch_source(P, s));
@@ -776,7 +805,8 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
     int cur = 0;
     bool timed[NQ] = {false, false, false, false};
     for (int pass = 0; pass < 100000; ++pass) {
-        HIPCHK(hipMemcpyAsync(c->host, cnt + cur * NQ, NQ * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(launch_seg_total(P, seg + cur * SEG_SET, cnt, s));
+        HIPCHK(hipMemcpyAsync(c->host, cnt, NQ * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(c->host + NQ, P.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int k = 0; k < NQ; ++k)
@@ -789,16 +819,16 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
             }
         uint32_t n[NQ];
         std::memcpy(n, c->host, sizeof n);
-        if (c->host[NQ] & (ERR_QUEUE | ERR_NAN | ERR_STEPS)) return check_error_word(c, c->host[NQ]);
+        if (c->host[NQ] & (ERR_QUEUE | ERR_NAN | ERR_STEPS | ERR_SAMPLE)) return check_error_word(c, c->host[NQ]);
         bool any = false;
         for (int k = 0; k < NQ; ++k) {
             any |= n[k] > 0;
             c->queue_peak = std::max<uint64_t>(c->queue_peak, n[k]);
         }
         if (!any) break;
-        // clear the other buffer's fill counts and all consume heads
-        HIPCHK(launch_zero(cnt + (1 - cur) * NQ, NQ * sizeof(uint32_t), s));
-        HIPCHK(launch_zero(cnt + 2 * NQ, NQ * sizeof(uint32_t), s));
+        // clear the other set's fill counters and all consume heads
+        HIPCHK(launch_zero(seg + (1 - cur) * SEG_SET, SEG_SET * 4, s));
+        HIPCHK(launch_zero(seg + 2 * SEG_SET, SEG_SET * 4, s));
         use(cur);
         for (int k = 0; k < NQ; ++k) {
             if (!n[k]) continue;

@@ -133,6 +133,26 @@ __device__ __forceinline__ void place(const Params &P, int region, Part &c, Loca
     append(P, S, QEE, kind == QEE, c);
 }
 
+// A photon outside the phantom box whose ray cannot enter it (it has just left the box on a
+// straight line, or it is a source photon whose ray misses the box): it reaches the EPID
+// front face within the image area, or it escapes.
+__device__ __forceinline__ void photon_leaves_phantom(const Params &P, Part &p, Local &L, Stages S)
+{
+    if (p.w > 0.0f) {
+        const float t = (P.ph_to_epid_z - p.z) / p.w;
+        const float xg = fmaf(t, p.u, p.x) + P.ox, yg = fmaf(t, p.v, p.y) + P.oy;
+        if (xg >= -P.hx && xg < P.hx && yg >= -P.hy && yg < P.hy) {
+            p.x = xg; p.y = yg; p.z = 0.0f;
+            p.flags &= ~F_LAYER_MASK;   // the front layer
+            ++L.entries;
+            if (p.flags & F_UNSCAT) ++L.unscat;
+            append(P, S, QGE, true, p);
+            return;
+        }
+    }
+    ledger(P, p.hist, (double)p.E);
+}
+
 // deposit at a point of `region` (phantom: ledger only; EPID: tallied in the scoring layer)
 __device__ __forceinline__ void deposit_point(const Params &P, int region, const Part &at, float e, Local &L)
 {
@@ -222,12 +242,12 @@ __device__ __forceinline__ bool kn_trial(const KN &c, float u1, float u2, float 
 {
     float e = u1 < c.pa ? __expf(-c.a1 * (u1 * c.ipa)) : sqrtf(fmaf(1.0f - c.e02, (u1 - c.pa) * c.iqa, c.e02));
     e = fminf(fmaxf(e, c.e0), 1.0f);
-    const float tt = (1.0f - e) * __frcp_rn(c.k * e);
-    const float g = 1.0f - e * (tt * (2.0f - tt)) * __frcp_rn(fmaf(e, e, 1.0f));
+    const float tt = (1.0f - e) / (c.k * e);
+    const float g = 1.0f - e * (tt * (2.0f - tt)) / fmaf(e, e, 1.0f);
     if (!(u2 < g)) return false;
     eps = e;
     t = fminf(tt, 2.0f);
-    phu = fminf(u2 * __frcp_rn(g), 0.99999994f);
+    phu = fminf(u2 / g, 0.99999994f);
     return true;
 }
 
@@ -270,12 +290,12 @@ __device__ __forceinline__ float highland(float T, float x, float X0)
 {
     if (!(x > 0.0f)) return 0.0f;
     const float E = T + MEC2F;
-    const float iE = __frcp_rn(E);
+    const float iE = 1.0f / E;
     const float pc2 = T * (T + 2.0f * MEC2F);
     const float b2 = pc2 * iE * iE;
-    const float r = __fdividef(x, X0);
-    const float br = fmaxf(0.0f, 1.0f + 0.038f * __logf(__fdividef(r, b2)));
-    return __fdividef(13.6f * E, pc2) * sqrtf(r) * br;
+    const float r = x / X0;
+    const float br = fmaxf(0.0f, 1.0f + 0.038f * __logf(r / b2));
+    return 13.6f * E / pc2 * sqrtf(r) * br;
 }
 
 // ---------------------------------------------------------------------------------
@@ -296,7 +316,7 @@ __device__ __forceinline__ bool compton_finish(const Params &P, int region, Part
     float eu = p.u, ev = p.v, ew = p.w;
     if (T > 0.0f) {
         const float pe = sqrtf(T * (T + 2.0f * MEC2F));
-        const float ipe = __frcp_rn(pe);
+        const float ipe = 1.0f / pe;
         const float cte = fminf(1.0f, (E - Ep * ct) * ipe), ste = fminf(1.0f, Ep * st * ipe);
         rotate(eu, ev, ew, cte, ste, -cp, -sp);
     }
@@ -416,17 +436,23 @@ __global__ __launch_bounds__(WG) void k_source(Params P)
                 Part q = p;
                 if (vacuum_phantom_frame(P, q) == 0) p = q;   // moved to its entry point
             }
-            qstore(P.out[QGP], (uint32_t)(h - P.h0), p);
+            // item j of the chunk goes to segment j / q at offset j % q, q = ceil(n / NSEG)
+            const uint32_t j = (uint32_t)(h - P.h0), q = (uint32_t)((P.h1 - P.h0 + NSEG - 1) / NSEG);
+            const uint32_t sg = j / q;
+            qstore(P.out[QGP], sg * P.segcap[QGP] + (j - sg * q), p);
         } else if (in_phantom(P, p.x, p.y, p.z)) {
             // a phase-space particle that starts inside the box is in the phantom
             const bool photon = type == 0;
-            qappend(P, QGP, photon, p);
-            qappend(P, QEP, !photon, p);
+            qappend(P, QGP, photon, p, home_seg());
+            qappend(P, QEP, !photon, p, home_seg());
         } else {
             place(P, 0, p, L);
         }
     }
-    if (!P.n_phsp && blockIdx.x == 0 && threadIdx.x == 0) P.cnt_out[QGP] = (uint32_t)(P.h1 - P.h0);
+    if (!P.n_phsp && blockIdx.x == 0 && threadIdx.x < NSEG) {
+        const uint32_t n = (uint32_t)(P.h1 - P.h0), q = (n + NSEG - 1) / NSEG, s0 = threadIdx.x * q;
+        *seg_ctr(P.cnt_out, QGP, threadIdx.x) = s0 < n ? min(q, n - s0) : 0u;
+    }
     // counters of direct hits on the EPID
     if (L.entries) atomicAdd(&P.stats[S_EPID_ENTRIES], (unsigned long long)L.entries);
     if (L.unscat) atomicAdd(&P.stats[S_UNSCAT], (unsigned long long)L.unscat);
@@ -435,126 +461,168 @@ __global__ __launch_bounds__(WG) void k_source(Params P)
 // ---------------------------------------------------------------------------------
 // photons in the phantom: Woodcock tracking
 // ---------------------------------------------------------------------------------
-template <bool TAB_LDS>
 __global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
 {
     // dynamic LDS: per wave two staging buffers (electrons for the phantom queue, photons
-    // for the EPID queue), then the tables when they are staged
+    // for the EPID queue).  The packed tables (16 KB of mu/rho, 32 KB of process fractions)
+    // stay in global memory, where they live in L2.
     extern __shared__ __align__(16) float lds[];
-    const int wave = wave_id();
-    constexpr int SWORDS = 2 * stage_words(SBUF);
     Stages S;
-    stage_carve(S, (uint32_t *)lds + (size_t)wave * SWORDS, (1u << QEP) | (1u << QGE), SBUF);
-    float *tabs = lds + (WG / 64) * SWORDS;
-    const int ntab = P.nmat_ph * 3 * NB_PH;
-    if (TAB_LDS) {
-        for (int i = threadIdx.x; i < ntab; i += WG) tabs[i] = P.ph_tab[i];
-        for (int i = threadIdx.x; i < NB_PH; i += WG) tabs[ntab + i] = P.ph_maj[i];
-    }
+    stage_carve(S, (uint32_t *)lds + (size_t)wave_id() * 2 * stage_words(SBUF), (1u << QEP) | (1u << QGE), SBUF);
     __syncthreads();
-    const float *tab = TAB_LDS ? tabs : P.ph_tab;
-    const float *maj = TAB_LDS ? tabs + ntab : P.ph_maj;
 
-    const uint32_t n = min(P.cnt_in[QGP], P.cap[QGP]);
-    Win win{0, 0, 0};
+    Win win = win_start();
     bool active = false;
     bool kn = false;   // a Compton collision whose Klein-Nishina sample is still pending
+    int kn_rounds = 0; // draws spent on it
     Part p;
     Local L;
     zero(L);
-    float imubar = 1.0f, mubar = 1.0f, mu0 = 0, mu1 = 0, mu2 = 0, mu3 = 0;
+    float imubar = 1.0f, mubar = 1.0f;
+    float4 mu = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // mu/rho of the four phantom slots at p.E
     Node nd{0, 0.0f};
     float e_cached = -1.0f;
     unsigned long long lane_iters = 0, wave_iters = 0;
     for (;;) {
         stage_flush_all(P, S, SBUF / 2);
         const bool was = active;
-        refill(P, QGP, n, win, active, p);
+        refill(P, QGP, win, active, p);
         const unsigned long long act = __ballot(active);
         if (act == 0) break;
         lane_iters += __popcll(act);
         wave_iters += 64;
+        // Control flow merges before every shared piece (the exit to the EPID, the Klein-
+        // Nishina trial, the electron emission), so that each is compiled once: a wave runs
+        // every piece that any of its lanes needs on every iteration.
+        bool leave = false;   // outside the box on a ray that cannot enter it: EPID or escape
         if (active && !was) {
             ++L.items;
             kn = false;
-            if (!in_phantom(P, p.x, p.y, p.z)) {
-                // a source photon whose ray misses the box: EPID or escape
-                place(P, 0, p, L, S);
-                active = false;
-            }
+            leave = !in_phantom(P, p.x, p.y, p.z);   // a source photon whose ray misses the box
         }
-        if (!active) continue;
-        if (p.E != e_cached) {
-            e_cached = p.E;
-            nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
-            mubar = lerp_tab(maj, nd);
-            imubar = 1.0f / mubar;
-            mu0 = lerp_tab(tab + 0 * 3 * NB_PH, nd);
-            if (P.nmat_ph > 1) mu1 = lerp_tab(tab + 1 * 3 * NB_PH, nd);
-            if (P.nmat_ph > 2) mu2 = lerp_tab(tab + 2 * 3 * NB_PH, nd);
-            if (P.nmat_ph > 3) mu3 = lerp_tab(tab + 3 * 3 * NB_PH, nd);
-        }
-        // One Philox draw per lane and iteration, so that every lane of the wave spends its
-        // random-number work together: a flight uses it for the distance, the real/virtual
-        // test, the process and the first Klein-Nishina trial; a pending Compton sample uses
-        // it for two further trials.
-        const float4 r = rnd4(p, P);
-        float eps = 1.0f, t = 0.0f, phu = 0.0f;
-        bool scatter = false;
-        if (kn) {
-            const KN c = kn_setup(p.E);
-            scatter = kn_trial(c, r.x, r.y, eps, t, phu) || kn_trial(c, r.z, r.w, eps, t, phu);
-        } else {
-            // a flight longer than the box chord leaves the box either way (and an empty
-            // phantom, mubar = 0, must not produce an infinite step)
-            const float s = fminf(-__logf(r.x) * imubar, P.chord);
-            p.x = fmaf(s, p.u, p.x);
-            p.y = fmaf(s, p.v, p.y);
-            p.z = fmaf(s, p.w, p.z);
-            ++L.steps;
-            if (!in_phantom(P, p.x, p.y, p.z)) {
-                // leaves the box on a straight line: EPID or escape
-                place(P, 0, p, L, S);
-                active = false;
-                continue;
+        if (active && !leave) {
+            if (p.E != e_cached) {
+                e_cached = p.E;
+                nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
+                const float4 a = P.ph_mu4[nd.i], b = P.ph_mu4[nd.i + 1];
+                mu.x = fmaf(nd.f, b.x - a.x, a.x);
+                mu.y = fmaf(nd.f, b.y - a.y, a.y);
+                mu.z = fmaf(nd.f, b.z - a.z, a.z);
+                mu.w = fmaf(nd.f, b.w - a.w, a.w);
+                // the majorant: each slot's largest density times its mu/rho, so that it bounds
+                // rho mu/rho of every voxel at this energy exactly as interpolated here
+                mubar = fmaxf(fmaxf(P.rmaj[0] * mu.x, P.rmaj[1] * mu.y), fmaxf(P.rmaj[2] * mu.z, P.rmaj[3] * mu.w));
+                imubar = 1.0f / mubar;
             }
-            const int ix = min((int)(p.x * P.idx), P.nx - 1), iy = min((int)(p.y * P.idy), P.ny - 1),
-                      iz = min((int)(p.z * P.idz), P.nz - 1);
-            const uint32_t word = P.vox[((uint32_t)iz * (uint32_t)P.ny + (uint32_t)iy) * (uint32_t)P.nx + (uint32_t)ix];
-            const float rho = __uint_as_float(word & ~3u);
-            const int m = (int)(word & 3u);
-            const float mum = m == 0 ? mu0 : m == 1 ? mu1 : m == 2 ? mu2 : mu3;
-            if (r.y * mubar < rho * mum) {
-                // a real collision: r.z picks the process, and within Compton, rescaled to
-                // (0, 1), it is the first trial's part-and-eps uniform
-                const float *mt = tab + m * 3 * NB_PH;
-                const float fc = lerp_tab(mt + NB_PH, nd);
-                p.flags &= ~F_UNSCAT;
-                if (r.z < fc) {
-                    ++L.compton;
-                    const KN c = kn_setup(p.E);
-                    scatter = kn_trial(c, fminf(r.z * __frcp_rn(fc), 0.99999994f), r.w, eps, t, phu);
-                    kn = !scatter;
-                } else {
-                    const float fcp = lerp_tab(mt + 2 * NB_PH, nd);
-                    if (r.z < fcp) photo_absorb(P, 0, p, L, S);
-                    else pair_produce(P, 0, p, r.w, L, S);
-                    active = false;
-                    continue;
+            // One Philox draw per lane and iteration, so that every lane of the wave spends its
+            // random-number work together: a flight uses it for the distance, the real/virtual
+            // test, the process and the first Klein-Nishina trial; a pending Compton sample
+            // uses it for two further trials.
+            const float4 r = rnd4(p, P);
+            bool trial = kn;       // a Klein-Nishina trial this iteration, from (u1, u2)
+            bool absorb = false;   // photoelectric absorption: the electron takes E along the photon
+            float u1 = r.x, u2 = r.y;
+            if (!kn) {
+                // a flight longer than the box chord leaves the box either way (and an empty
+                // phantom, mubar = 0, must not produce an infinite step)
+                const float s = fminf(-__logf(r.x) * imubar, P.chord);
+                p.x = fmaf(s, p.u, p.x);
+                p.y = fmaf(s, p.v, p.y);
+                p.z = fmaf(s, p.w, p.z);
+                ++L.steps;
+                leave = !in_phantom(P, p.x, p.y, p.z);   // left the box on a straight line
+                if (!leave) {
+                    const int ix = min((int)(p.x * P.idx), P.nx - 1), iy = min((int)(p.y * P.idy), P.ny - 1),
+                              iz = min((int)(p.z * P.idz), P.nz - 1);
+                    const uint32_t word =
+                        P.vox[((uint32_t)iz * (uint32_t)P.ny + (uint32_t)iy) * (uint32_t)P.nx + (uint32_t)ix];
+                    const float rho = __uint_as_float(word & ~3u);
+                    const int m = (int)(word & 3u);
+                    const float mum = m == 0 ? mu.x : m == 1 ? mu.y : m == 2 ? mu.z : mu.w;
+                    if (r.y * mubar < rho * mum) {
+                        // a real collision: r.z picks the process, and within Compton, rescaled
+                        // to (0, 1), it is the first trial's part-and-eps uniform
+                        const float2 fa = P.ph_fr[m * NB_PH + nd.i], fb = P.ph_fr[m * NB_PH + nd.i + 1];
+                        const float fc = fmaf(nd.f, fb.x - fa.x, fa.x);
+                        p.flags &= ~F_UNSCAT;
+                        if (r.z < fc) {
+                            ++L.compton;
+                            trial = true;
+                            u1 = fminf(r.z / fc, 0.99999994f);
+                            u2 = r.w;
+                        } else if (r.z < fmaf(nd.f, fb.y - fa.y, fa.y)) {
+                            ++L.photo;
+                            absorb = true;
+                        } else {
+                            pair_produce(P, 0, p, r.w, L, S);   // rare: kept out of the merged path
+                            active = false;
+                        }
+                    }
                 }
             }
+            float eps = 1.0f, t = 0.0f, phu = 0.0f;
+            bool scatter = false;
+            if (trial) {
+                const KN c = kn_setup(p.E);
+#pragma unroll 1
+                for (int k = 0; k < 2; ++k) {
+                    scatter = kn_trial(c, u1, u2, eps, t, phu);
+                    if (scatter || !kn) break;
+                    u1 = r.z;   // a pending sample gets a second trial from the same draw
+                    u2 = r.w;
+                }
+                kn_rounds = kn ? kn_rounds + 1 : 0;
+                kn = !scatter;
+                if (kn && kn_rounds > MAX_KN_ROUNDS) {
+                    // unreachable with a sound generator; ends the lane so the wave drains
+                    atomicOr(P.err, ERR_SAMPLE);
+                    ledger(P, p.hist, (double)p.E);
+                    kn = false;
+                    active = false;
+                }
+            }
+            if (scatter || absorb) {
+                // one electron set in motion at p: after a Compton scatter it carries the
+                // momentum the photon lost, after absorption the photon's energy and direction
+                const float E = p.E;
+                float eT = E, eu = p.u, ev = p.v, ew = p.w;
+                active = false;
+                if (scatter) {
+                    const float ct = 1.0f - t, st = sqrtf(fmaxf(0.0f, t * (2.0f - t)));
+                    float sp, cp;
+                    __sincosf(TWO_PI_F * phu, &sp, &cp);
+                    const float Ep = eps * E;
+                    eT = E - Ep;
+                    if (P.diag) ledger(P, p.hist, (double)E - (double)Ep - (double)eT);
+                    rotate(p.u, p.v, p.w, ct, st, cp, sp);
+                    const float qx = fmaf(-Ep, p.u, E * eu), qy = fmaf(-Ep, p.v, E * ev), qz = fmaf(-Ep, p.w, E * ew);
+                    const float q2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+                    if (q2 > 0.0f) {
+                        const float iq = rsqrtf(q2);
+                        eu = qx * iq; ev = qy * iq; ew = qz * iq;
+                    }
+                    p.E = Ep;
+                    active = Ep >= P.pcut;
+                    if (!active) ledger(P, p.hist, (double)Ep);
+                }
+                Part c;
+                make_child(p, c, 1u);
+                c.x = p.x; c.y = p.y; c.z = p.z;
+                c.u = eu; c.v = ev; c.w = ew;
+                c.E = eT;
+                if (!P.coupled || eT < P.ecut) ledger(P, c.hist, (double)eT);
+                else append(P, S, QEP, true, c);
+            }
         }
-        if (scatter) {
-            kn = false;
-            active = compton_finish(P, 0, p, eps, t, phu, L, S);
+        if (leave) {
+            photon_leaves_phantom(P, p, L, S);
+            active = false;
         }
     }
     stage_flush_all(P, S, 1);
     flush_stats(P, L, S_WOODCOCK, QGP, lane_iters, wave_iters);
 }
 
-template __global__ void k_photon_phantom<true>(Params);
-template __global__ void k_photon_phantom<false>(Params);
 
 // ---------------------------------------------------------------------------------
 // photons in the EPID: exact tracking across the slabs
@@ -574,8 +642,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
     if (threadIdx.x < MAX_LAYERS) s_rho[threadIdx.x] = P.lrho[threadIdx.x];
     __syncthreads();
 
-    const uint32_t n = min(P.cnt_in[QGE], P.cap[QGE]);
-    Win win{0, 0, 0};
+    Win win = win_start();
     bool active = false;
     Part p;
     Local L;
@@ -584,7 +651,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
     for (;;) {
         stage_flush_all(P, S, SBUF / 2);
         const bool was = active;
-        refill(P, QGE, n, win, active, p);
+        refill(P, QGE, win, active, p);
         const unsigned long long act = __ballot(active);
         if (act == 0) break;
         lane_iters += __popcll(act);
@@ -664,8 +731,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
     const int region = EPID ? 1 : 0;
     const float ln09 = -0.105360515657826301f;   // ln 0.9
 
-    const uint32_t n = min(P.cnt_in[kind], P.cap[kind]);
-    Win win{0, 0, 0};
+    Win win = win_start();
     bool active = false;
     Part p;
     // positions advance in FP64: a 0.1 um nudge must move a particle across a face even
@@ -678,7 +744,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
     for (;;) {
         stage_flush_all(P, S, SBUF_E / 2);
         const bool was = active;
-        refill(P, kind, n, win, active, p);
+        refill(P, kind, win, active, p);
         const unsigned long long act = __ballot(active);
         if (act == 0) break;
         lane_iters += __popcll(act);
@@ -726,9 +792,9 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
         // distance to the cell faces: the offset to the face is taken in FP64, then the small
         // difference is divided in FP32
         float dg = INFINITY;
-        if (p.u != 0.0f) dg = fminf(dg, (float)((p.u > 0.0f ? hi0 : lo0) - px) * __frcp_rn(p.u));
-        if (p.v != 0.0f) dg = fminf(dg, (float)((p.v > 0.0f ? hi1 : lo1) - py) * __frcp_rn(p.v));
-        if (p.w != 0.0f) dg = fminf(dg, (float)((p.w > 0.0f ? hi2 : lo2) - pz) * __frcp_rn(p.w));
+        if (p.u != 0.0f) dg = fminf(dg, (float)((p.u > 0.0f ? hi0 : lo0) - px) / p.u);
+        if (p.v != 0.0f) dg = fminf(dg, (float)((p.v > 0.0f ? hi1 : lo1) - py) / p.v);
+        if (p.w != 0.0f) dg = fminf(dg, (float)((p.w > 0.0f ? hi2 : lo2) - pz) / p.w);
         const float sg = fmaxf(fmaxf(dg, 0.0f) + NUDGE, smin);
         float T = p.E;
         if (!(rho > 0.0f)) {
@@ -745,7 +811,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
             const float R9 = lerp_tab(tab, n9);
             const float4 r = rnd4(p, P);
             const float irho = 1.0f / rho;
-            const float s_hard = sh > 0.0f ? __fdividef(-__logf(r.x), rho * sh) : INFINITY;
+            const float s_hard = sh > 0.0f ? -__logf(r.x) / (rho * sh) : INFINITY;
             const float s_de = (R0 - R9) * irho;
             const float s_pix = (EPID && layer == P.scoring) ? P.s_pix : INFINITY;
             const float s = fminf(fminf(s_hard, s_de), fminf(sg, s_pix));
@@ -762,7 +828,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                     if (tab[mid] <= Rt) lo = mid; else hi = mid;
                 }
                 const float d = tab[lo + 1] - tab[lo];
-                const float f = d > 0.0f ? fminf(fmaxf(__fdividef(Rt - tab[lo], d), 0.0f), 1.0f) : 0.0f;
+                const float f = d > 0.0f ? fminf(fmaxf((Rt - tab[lo]) / d, 0.0f), 1.0f) : 0.0f;
                 T1 = fminf(__expf(P.el_lnT0 + ((float)lo + f) / P.el_idl), T);
             }
             // hinge point: the step's continuous loss is deposited there
@@ -1021,6 +1087,18 @@ __global__ void k_diag_check(Params P, uint32_t nh, unsigned long long *maxbits,
     unsafeAtomicAdd(&sums[1], led);
 }
 
+// particles in each queue after a pass: the sum over its segments of min(fill, segcap);
+// one workgroup, wave k sums queue k (NSEG = 64 segments, one per lane)
+static_assert(NSEG == 64 && WG == 64 * NQ, "one lane per segment, one wave per queue");
+__global__ void k_seg_total(Params P, const uint32_t *cnt, uint32_t *tot)
+{
+    const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t v = min(cnt[((uint32_t)k * NSEG + lane) * CSTRIDE], P.segcap[k]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) tot[k] = v;
+}
+
 __global__ void k_zero_u32(uint32_t *a, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = 0;
@@ -1123,11 +1201,6 @@ __global__ void k_dbg_source(Params P, unsigned long long h0, float *out, unsign
 // ---------------------------------------------------------------------------------
 static inline unsigned grid_for(unsigned long long n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
-// the Woodcock kernel touches its tables only when a photon's energy changes, so they are
-// read through the caches; LDS holds the staged appends instead (0 = tables in L1/L2)
-#ifndef PH_TAB_LDS
-#define PH_TAB_LDS 0
-#endif
 
 hipError_t launch_source(const Params &P, hipStream_t s)
 {
@@ -1140,7 +1213,7 @@ hipError_t launch_source(const Params &P, hipStream_t s)
 size_t lds_bytes(int kind, const Params &P)
 {
     switch (kind) {
-    case QGP: return (size_t)(WG / 64) * 2 * stage_words(SBUF) * 4 + (PH_TAB_LDS ? (size_t)(P.nmat_ph * 3 + 1) * NB_PH * 4 : 0);
+    case QGP: return (size_t)(WG / 64) * 2 * stage_words(SBUF) * 4;
     case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float) + (size_t)(WG / 64) * stage_words(SBUF) * 4;
     case QEP: return (size_t)P.nmat_ph * 3 * NB_EL * sizeof(float) + (size_t)(WG / 64) * 4 * stage_words(SBUF_E) * 4;
     default: return (size_t)P.nl * 3 * NB_EL * sizeof(float) + (size_t)(WG / 64) * 2 * stage_words(SBUF_E) * 4;
@@ -1151,7 +1224,7 @@ hipError_t launch_transport(int kind, const Params &P, unsigned blocks, hipStrea
 {
     const size_t lds = lds_bytes(kind, P);
     switch (kind) {
-    case QGP: hipLaunchKernelGGL(k_photon_phantom<PH_TAB_LDS>, dim3(blocks), dim3(WG), lds, s, P); break;
+    case QGP: hipLaunchKernelGGL(k_photon_phantom, dim3(blocks), dim3(WG), lds, s, P); break;
     case QGE: hipLaunchKernelGGL(k_photon_epid, dim3(blocks), dim3(WG), lds, s, P); break;
     case QEP: hipLaunchKernelGGL(k_electron<false>, dim3(blocks), dim3(WG), lds, s, P); break;
     default: hipLaunchKernelGGL(k_electron<true>, dim3(blocks), dim3(WG), lds, s, P); break;
@@ -1164,7 +1237,7 @@ hipError_t set_lds_limits()
     // allow the dynamic LDS sizes above the default 64 KiB cap
     hipError_t e = hipSuccess;
     const int big = 160 * 1024;
-    e = hipFuncSetAttribute((const void *)k_photon_phantom<PH_TAB_LDS>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    e = hipFuncSetAttribute((const void *)k_photon_phantom, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_photon_epid, hipFuncAttributeMaxDynamicSharedMemorySize, big);
     if (e != hipSuccess) return e;
@@ -1220,6 +1293,12 @@ hipError_t launch_sigma_bar(const Params &P, double n, double nb, double thr, do
 hipError_t launch_diag_check(const Params &P, uint32_t nh, unsigned long long *maxbits, double *sums, hipStream_t s)
 {
     hipLaunchKernelGGL(k_diag_check, dim3(min(grid_for(nh, 256), 2048u)), dim3(256), 0, s, P, nh, maxbits, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_total(const Params &P, const uint32_t *cnt, uint32_t *tot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_seg_total, dim3(1), dim3(WG), 0, s, P, cnt, tot);
     return hipGetLastError();
 }
 
