@@ -31,6 +31,7 @@ ALU_PEAK_OPS = 256 * 64 * 2.4e9
 # algorithmic VALU lane-operations per unit of work ("Roofline")
 OPS_PER_UNIT = {"electron_step": 310, "woodcock_step": 120, "epid_photon_step": 130}
 KIND = ["photon_phantom", "electron_phantom", "photon_epid", "electron_epid"]
+KERNEL = ["k_photon_phantom", "k_electron<phantom>", "k_photon_epid", "k_electron<epid>"]
 
 
 def kernel_source_sha():
@@ -47,14 +48,15 @@ def profiled_traffic(kernel):
     was taken on the current kernel sources."""
     import glob
     sha = kernel_source_sha()
+    key = f"traffic_bytes_per_launch[{kernel}]"
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         kv = {}
         for line in open(f):
             parts = line.strip().split(": ", 1)
             if len(parts) == 2:
                 kv[parts[0]] = parts[1]
-        if kv.get("traffic_kernel") == kernel and kv.get("source_sha") == sha:
-            return float(kv["traffic_bytes_per_launch"]), os.path.basename(f)
+        if kv.get("source_sha") == sha and key in kv:
+            return float(kv[key]), os.path.basename(f)
     return None, None
 
 
@@ -65,7 +67,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--histories", type=int, default=HISTORIES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=300_000)
+    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -115,7 +117,7 @@ def main():
     avg_s = c["kernel_ms"][dom] / 1e3 / launches
     ops_per_launch = units[dom] * per[dom] / launches
     achieved = ops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
-    kname = "k_electron<phantom>" if dom == 1 else KIND[dom]
+    kname = KERNEL[dom]
     traffic, tsrc = profiled_traffic(kname)
     roof = {"bound": "alu", "kernel": kname,
             "achieved": round(achieved, 3), "peak": round(ALU_PEAK_OPS / 1e12, 3), "unit": "Tlane-op/s",
