@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 HISTORIES = 100_000_000
 BATCHES = 64
-CHUNK = 1 << 25
+CHUNK = 1 << 27   # one chunk per 1e8-history step: fewer queue passes and launch tails
 # peak plain-ALU issue rate of MI355X: 256 CUs x 64 lanes x 2.4 GHz (one VALU op per lane per
 # clock; FMA and packed FP32 doubling excluded because the hot path is not FMA-bound)
 ALU_PEAK_OPS = 256 * 64 * 2.4e9

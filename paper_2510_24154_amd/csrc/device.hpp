@@ -107,32 +107,24 @@ __device__ __forceinline__ uint32_t *seg_ctr(uint32_t *base, int kind, uint32_t 
 // per workgroup and NSEG = 64 every segment is used by the waves of a single XCD.
 __device__ __forceinline__ uint32_t home_seg() { return ((uint32_t)blockIdx.x * (WG / 64) + (uint32_t)wave_id()) % NSEG; }
 
-// Append to the next-pass queue of `kind`: the executing lanes with `pred` set take
-// consecutive slots of segment `seg`, one atomic per wave; lanes that find the segment full
-// move on to the next segment.  Valid in divergent code: the ballot only sees the executing
-// lanes and the leader is one of them.  A particle that finds every segment full is dropped
-// and the overflow is latched in the error word.
+// Append to a next-pass queue: the executing lanes with `pred` set take consecutive slots of
+// segment `seg`, one atomic per wave.  Valid in divergent code: the ballot only sees the
+// executing lanes and the leader is one of them.  Segments are sized at 1/NSEG of a queue
+// whose capacity is several times what a chunk produces, so a full segment means the chunk
+// is too large for the workspace: the particle is dropped and the overflow latched.
 __device__ __forceinline__ void qappend(const Params &P, int kind, bool pred, const Part &p, uint32_t seg)
 {
-    bool pending = pred;
-    const uint32_t cap = P.segcap[kind];
-    for (int tries = 0; tries < NSEG; ++tries) {
-        const unsigned long long m = __ballot(pending);
-        if (m == 0) return;
-        const int leader = __ffsll((long long)m) - 1;
-        uint32_t base = 0;
-        if ((int)lane_id() == leader) base = atomicAdd(seg_ctr(P.cnt_out, kind, seg), (uint32_t)__popcll(m));
-        base = __shfl(base, leader);
-        if (pending) {
-            const uint32_t i = base + (uint32_t)__popcll(m & __lanemask_lt());
-            if (i < cap) {
-                qstore(P.out[kind], seg * cap + i, p);
-                pending = false;
-            }
-        }
-        seg = (seg + 1) % NSEG;
+    const unsigned long long m = __ballot(pred);
+    if (m == 0) return;
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd(seg_ctr(P.cnt_out, kind, seg), (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) {
+        const uint32_t i = base + (uint32_t)__popcll(m & __lanemask_lt());
+        if (i < P.segcap[kind]) qstore(P.out[kind], seg * P.segcap[kind] + i, p);
+        else atomicOr(P.err, ERR_QUEUE);
     }
-    if (pending) atomicOr(P.err, ERR_QUEUE);
 }
 
 // ---------------------------------------------------------------------------------
@@ -146,7 +138,7 @@ __device__ __forceinline__ void qappend(const Params &P, int kind, bool pred, co
 struct Stages {
     uint32_t *w[NQ];
     uint32_t sb;
-    uint32_t seg;   // the segment the wave's flushes go to (advances when it fills)
+    uint32_t seg;   // the wave's home segment, where its flushes go
 };
 
 __host__ __device__ constexpr int stage_words(int sb) { return 12 * sb + 4; }
@@ -200,19 +192,14 @@ __device__ __forceinline__ void stage_flush(const Params &P, Stages &S, int kind
     const uint32_t n =
         min(__hip_atomic_load(w + 12 * S.sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT), S.sb);
     if (n == 0 || n < minfill) return;
-    // reserve in the wave's current segment; what does not fit goes to the next one
+    // one reservation in the wave's home segment (a full segment: see qappend)
     const uint32_t cap = P.segcap[kind];
-    uint32_t done = 0;
-    for (int tries = 0; tries < NSEG && done < n; ++tries) {
-        uint32_t base = 0;
-        if (lane_id() == 0) base = atomicAdd(seg_ctr(P.cnt_out, kind, S.seg), n - done);
-        base = __shfl(base, 0);
-        const uint32_t fit = base < cap ? min(n - done, cap - base) : 0u;
-        for (uint32_t i = lane_id(); i < fit; i += 64) stage_copy(P.out[kind], S.seg * cap + base + i, w, S.sb, done + i);
-        done += fit;
-        if (done < n) S.seg = (S.seg + 1) % NSEG;
-    }
-    if (done < n && lane_id() == 0) atomicOr(P.err, ERR_QUEUE);
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(seg_ctr(P.cnt_out, kind, S.seg), n);
+    base = __shfl(base, 0);
+    const uint32_t fit = base < cap ? min(n, cap - base) : 0u;
+    for (uint32_t i = lane_id(); i < fit; i += 64) stage_copy(P.out[kind], S.seg * cap + base + i, w, S.sb, i);
+    if (fit < n && lane_id() == 0) atomicOr(P.err, ERR_QUEUE);
     __builtin_amdgcn_wave_barrier();
     if (lane_id() == 0) __hip_atomic_store(w + 12 * S.sb, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     __builtin_amdgcn_wave_barrier();
