@@ -144,8 +144,15 @@ def main():
         tc = time.perf_counter()
         oracle.run(cfg, ns, seed=1001, first=0, threads=threads)
         tcd = time.perf_counter() - tc
+        # the same oracle on one core, over a tenth of the sample
+        n1 = max(1000, ns // 10 // max(1, threads // 8))
+        t1c = time.perf_counter()
+        oracle.run(cfg, n1, seed=1001, first=0, threads=1)
+        t1d = time.perf_counter() - t1c
         cpu = {"value": round(ns / tcd, 1), "unit": "histories/s", "cores": threads, "kind": "oracle",
-               "sample": f"{ns} histories of the same workload (ids 0..{ns - 1}), {tcd:.1f} s wall on {threads} threads"}
+               "sample": f"{ns} histories of the same workload (ids 0..{ns - 1}), {tcd:.1f} s wall on {threads} threads",
+               "value_1core": round(n1 / t1d, 1),
+               "sample_1core": f"{n1} histories (ids 0..{n1 - 1}), {t1d:.1f} s on 1 thread"}
 
     out = {
         "metric": "photon histories/s (coupled transport to a 1% EPID image)",
