@@ -107,6 +107,12 @@ def lib():
             L.orc_photon_mu.restype = None
             L.orc_philox4x32_10.argtypes = [p, p, p]
             L.orc_philox4x32_10.restype = None
+            L.orc_radiological_thickness.argtypes = [ct.POINTER(Config), p]
+            L.orc_radiological_thickness.restype = ct.c_int
+            L.orc_equivalent_square.argtypes = [ct.POINTER(Config)]
+            L.orc_equivalent_square.restype = d
+            L.orc_response_factor.argtypes = [p, ct.c_int, p, ct.c_int, p, d, d]
+            L.orc_response_factor.restype = d
             _lib = L
     return _lib
 
@@ -236,3 +242,34 @@ def run(cfg: dict, n: int, seed: int = 1001, first: int = 0, threads: int = 1, p
     mean = s / n
     var = (s2 / n - mean * mean) / max(1, n - 1)
     return mean.reshape(P.shape), np.maximum(var, 0).reshape(P.shape), s, s2, cnt
+
+
+def radiological_thickness(cfg: dict) -> np.ndarray:
+    """Radiological thickness (cm of unit density) of the phantom along each pixel's ray,
+    shape (npx_v, npx_u) (Sec. 2.2, item 1)."""
+    P = Prepared(cfg, 0)
+    out = np.zeros(P.npix)
+    if lib().orc_radiological_thickness(ct.byref(P.c), out.ctypes.data) != 0:
+        raise ValueError("orc_radiological_thickness failed")
+    return out.reshape(P.shape)
+
+
+def equivalent_square(cfg: dict) -> float:
+    """Equivalent square (cm) of the open aperture's bounding rectangle (Sec. 2.2, Eq. 1)."""
+    P = Prepared(cfg, 0)
+    return float(lib().orc_equivalent_square(ct.byref(P.c)))
+
+
+def response_factor(t_nodes, s_nodes, k, t, s) -> np.ndarray:
+    """k(t, s) by clamped bilinear interpolation on the table k[s_j][t_i] (Eq. 2, Table 1);
+    t and s may be arrays of the same shape."""
+    tn = np.ascontiguousarray(t_nodes, dtype=np.float64)
+    sn = np.ascontiguousarray(s_nodes, dtype=np.float64)
+    kk = np.ascontiguousarray(k, dtype=np.float64).reshape(sn.size, tn.size)
+    t = np.asarray(t, dtype=np.float64)
+    s = np.broadcast_to(np.asarray(s, dtype=np.float64), t.shape)
+    f = lib().orc_response_factor
+    out = np.array([f(tn.ctypes.data, tn.size, sn.ctypes.data, sn.size, kk.ctypes.data, float(a), float(b))
+                    for a, b in zip(t.ravel(), s.ravel())])
+    return out.reshape(t.shape)
+

@@ -920,3 +920,128 @@ int orc_run(const orc_config *cf, uint64_t first, uint64_t count, double *sum, d
     free(c->hacc); free(c->touched); free(c); free(g.mu_cache);
     return err;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* dose-response correction inputs (Sec. 2.2, Sec. 3.1)                                 */
+/* ------------------------------------------------------------------------------------ */
+static int cmp_double(const void *x, const void *y)
+{
+    const double a = *(const double *)x, b = *(const double *)y;
+    return (a > b) - (a < b);
+}
+
+/* line integral of the density along the segment S -> T (g/cm^2) */
+static double ray_density_integral(const orc_config *cf, const double S[3], const double T[3], double *buf)
+{
+    const int n[3] = { cf->nx, cf->ny, cf->nz };
+    double d[3], lo[3], hi[3];
+    double amin = 0.0, amax = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        d[a] = T[a] - S[a];
+        lo[a] = cf->origin[a];
+        hi[a] = cf->origin[a] + n[a] * cf->spacing[a];
+        if (d[a] == 0.0) {
+            if (S[a] < lo[a] || S[a] >= hi[a]) return 0.0;   /* parallel to the slab and outside it */
+        } else {
+            double a1 = (lo[a] - S[a]) / d[a], a2 = (hi[a] - S[a]) / d[a];
+            if (a1 > a2) { double t = a1; a1 = a2; a2 = t; }
+            if (a1 > amin) amin = a1;
+            if (a2 < amax) amax = a2;
+        }
+    }
+    if (!(amax > amin)) return 0.0;
+    /* the crossings: the entry and exit parameters and every voxel plane strictly between */
+    int m = 0;
+    buf[m++] = amin;
+    buf[m++] = amax;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) continue;
+        for (int i = 0; i <= n[a]; ++i) {
+            const double al = (lo[a] + i * cf->spacing[a] - S[a]) / d[a];
+            if (al > amin && al < amax) buf[m++] = al;
+        }
+    }
+    qsort(buf, (size_t)m, sizeof(double), cmp_double);
+    const double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double sum = 0.0;
+    for (int k = 0; k + 1 < m; ++k) {
+        const double a0 = buf[k], a1 = buf[k + 1];
+        if (!(a1 > a0)) continue;
+        const double mid = 0.5 * (a0 + a1);
+        int idx[3];
+        for (int a = 0; a < 3; ++a) {
+            int i = (int)floor((S[a] + mid * d[a] - lo[a]) / cf->spacing[a]);
+            idx[a] = i < 0 ? 0 : (i >= n[a] ? n[a] - 1 : i);
+        }
+        sum += cf->vox_rho[((size_t)idx[2] * cf->ny + idx[1]) * cf->nx + idx[0]] * (a1 - a0) * len;
+    }
+    return sum;
+}
+
+int orc_radiological_thickness(const orc_config *cf, double *out)
+{
+    if (!cf || !out || cf->scoring_layer < 0 || cf->scoring_layer >= cf->n_layers) return ORC_E_ARG;
+    double zmid = cf->front_z;
+    for (int l = 0; l < cf->scoring_layer; ++l) zmid += cf->layer_t[l];
+    zmid += 0.5 * cf->layer_t[cf->scoring_layer];
+    const double hx = 0.5 * cf->npx_u * cf->pitch_u, hy = 0.5 * cf->npx_v * cf->pitch_v;
+    const double zlo = cf->origin[2], zhi = cf->origin[2] + cf->nz * cf->spacing[2];
+    double *buf = (double *)malloc(sizeof(double) * (size_t)(cf->nx + cf->ny + cf->nz + 8));
+    if (!buf) return ORC_E_ARG;
+    for (int v = 0; v < cf->npx_v; ++v)
+        for (int u = 0; u < cf->npx_u; ++u) {
+            const double x = -hx + (u + 0.5) * cf->pitch_u, y = -hy + (v + 0.5) * cf->pitch_v;
+            double S[3], T[3];
+            if (cf->beam_kind == 1) {
+                S[0] = cf->src[0]; S[1] = cf->src[1]; S[2] = cf->src[2];
+                T[0] = x; T[1] = y; T[2] = zmid;
+            } else {   /* parallel beam: a line along +z through the pixel centre, past the box */
+                S[0] = x; S[1] = y; S[2] = zlo - 1.0;
+                T[0] = x; T[1] = y; T[2] = zhi + 1.0;
+            }
+            out[(size_t)v * cf->npx_u + u] = ray_density_integral(cf, S, T, buf);   /* g/cm^2 over 1 g/cm^3 */
+        }
+    free(buf);
+    return ORC_OK;
+}
+
+double orc_equivalent_square(const orc_config *cf)
+{
+    double xmin = INFINITY, xmax = -INFINITY;
+    int kmin = -1, kmax = -1;
+    for (int s = 0; s < cf->n_seg; ++s)
+        for (int k = 0; k < cf->n_pairs; ++k) {
+            const double a = cf->a[(size_t)s * cf->n_pairs + k], b = cf->b[(size_t)s * cf->n_pairs + k];
+            if (!(b > a)) continue;   /* closed pair */
+            if (a < xmin) xmin = a;
+            if (b > xmax) xmax = b;
+            if (kmin < 0 || k < kmin) kmin = k;
+            if (k > kmax) kmax = k;
+        }
+    if (kmin < 0) return 0.0;
+    const double A = xmax - xmin, B = (kmax + 1 - kmin) * cf->leaf_w;
+    return 2.0 * A * B / (A + B);
+}
+
+/* the interval [x_i, x_{i+1}] of an ascending node list holding x (clamped), and the weight of x_{i+1} */
+static void bracket(const double *x, int n, double v, int *i_out, double *f_out)
+{
+    if (n == 1 || v <= x[0]) { *i_out = 0; *f_out = 0.0; return; }
+    if (v >= x[n - 1]) { *i_out = n - 2; *f_out = 1.0; return; }
+    int i = 0;
+    while (i + 1 < n - 1 && v >= x[i + 1]) ++i;
+    *i_out = i;
+    *f_out = (v - x[i]) / (x[i + 1] - x[i]);
+}
+
+double orc_response_factor(const double *tn, int nt, const double *sn, int ns, const double *k, double t, double s)
+{
+    int i, j;
+    double ft, fs;
+    bracket(tn, nt, t, &i, &ft);
+    bracket(sn, ns, s, &j, &fs);
+    const int i1 = nt > 1 ? i + 1 : i, j1 = ns > 1 ? j + 1 : j;
+    const double k00 = k[j * nt + i], k01 = k[j * nt + i1], k10 = k[j1 * nt + i], k11 = k[j1 * nt + i1];
+    return (1.0 - fs) * ((1.0 - ft) * k00 + ft * k01) + fs * ((1.0 - ft) * k10 + ft * k11);
+}
+

@@ -133,6 +133,24 @@ double orc_x0(const orc_material *m);                 /* radiation length, g/cm^
 double orc_highland(double T, double x_gcm2, double X0);
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
+/* ---- inputs of the EPID dose-response correction (Sec. 2.2, Sec. 3.1) ---- */
+/* Radiological thickness t of the phantom along each pixel's ray, in cm of unit density:
+ * the line integral of the voxel density divided by 1 g/cm^3 (Sec. 2.2, item 1).  A
+ * point source's ray runs from the source to the pixel centre on the mid-plane of the
+ * scoring layer; a parallel beam's runs along +z through the pixel centre.  out[v*npx_u+u].
+ * Siddon's method in FP64: every crossing of the ray with a voxel plane inside the box,
+ * merged in order; each piece between two crossings contributes its length times the
+ * density of the voxel that holds its midpoint. */
+int    orc_radiological_thickness(const orc_config *cfg, double *out);
+/* the equivalent square (cm) of the bounding rectangle of the open aperture over all
+ * segments, at the aperture plane (Sec. 2.2, item 2; Eq. 1 read as 4A/P: s = 2ab/(a+b)) */
+double orc_equivalent_square(const orc_config *cfg);
+/* k(t,s) by bilinear interpolation on a rectilinear table: t_nodes[nt] and s_nodes[ns]
+ * ascending, k[j*nt + i] the factor at (t_i, s_j); outside the table, t and s are clamped to
+ * its edges (Eq. 2, Table 1) */
+double orc_response_factor(const double *t_nodes, int nt, const double *s_nodes, int ns, const double *k,
+                           double t, double s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -221,3 +221,16 @@ def with_histories_scaled(cfg, total):
     n[np.argmax(n)] += total - int(n.sum())
     ap["counts"] = n.astype(np.uint64)
     return cfg
+
+
+def response_table_1():
+    """The EPID dose-response correction factors k(t, s) the paper measured (Sec. 3.1, Eq. 2,
+    Table 1): thickness nodes t (cm of solid water), field-side nodes s (cm), and k[j][i] at
+    (t_i, s_j).  Input data for the correction; no arithmetic on it here."""
+    t = np.array([0.0, 5.0, 10.0, 15.0, 20.0])
+    s = np.array([5.0, 10.0, 15.0, 20.0])
+    k = np.array([[0.999, 0.974, 0.960, 0.949, 0.949],
+                  [1.001, 0.975, 0.967, 0.964, 0.953],
+                  [0.995, 0.982, 0.983, 0.996, 0.986],
+                  [0.991, 0.997, 1.015, 1.034, 1.043]])
+    return t, s, k

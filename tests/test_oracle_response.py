@@ -1,0 +1,158 @@
+"""Pins of the oracle's dose-response inputs (Sec. 2.2 and 3.1): the radiological-thickness
+map, the equivalent field size and the k(t, s) interpolation, each against something other
+than the oracle's own code: exact chords, slab sums over cos(theta), a brute-force Riemann
+sum along the ray, area over perimeter, and the paper's Table 1 (tests/golden)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2510_24154_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_response_factors.txt")
+
+
+def golden_table1():
+    rows = [ln.split() for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
+    t = np.array([float(c.split("=")[1]) for c in rows[0][1:]])
+    s = np.array([float(r[0]) for r in rows[1:]])
+    k = np.array([[float(x) for x in r[1:]] for r in rows[1:]])
+    return t, s, k
+
+
+def slab_case(slabs, xy=40.0, beam=1, src_z=0.0, front_z=150.0, npx=24, pitch=1.0):
+    """A phantom of z slabs [(rho, thickness)] 2 voxels wide in x and y (each xy/2 cm),
+    starting at z = 80, and a one-layer EPID."""
+    cfg = synth.kerma_water(npx=npx, pitch=pitch)
+    nz = len(slabs)
+    cfg["phantom"] = {"kind": "direct", "shape": (2, 2, nz), "spacing": (xy / 2, xy / 2, 1.0),
+                      "origin": (-xy / 2, -xy / 2, 80.0), "mat": np.zeros(4 * nz, np.uint8),
+                      "rho": np.repeat(np.array([r for r, _ in slabs]), 4)}
+    cfg["phantom"]["spacing"] = (xy / 2, xy / 2, 1.0)
+    cfg["epid"] = {"layers": [{"mat": 1, "t": 0.2, "rho": 8.96}, {"mat": 2, "t": 0.04, "rho": 7.44}], "scoring": 1,
+                   "front_z": front_z, "npx_u": npx, "npx_v": npx, "pitch_u": pitch, "pitch_v": pitch}
+    cfg["source"]["beam"] = {"kind": beam, "src": (0.0, 0.0, src_z), "iso_z": 100.0}
+    return cfg
+
+
+def test_thickness_parallel_beam_uniform_box(orc):
+    """20 cm of unit-density water under a parallel beam: t = 20 cm exactly where the pixel
+    centre lies over the box, 0 elsewhere."""
+    cfg = synth.kerma_water(npx=32, pitch=0.8)
+    t = orc.radiological_thickness(cfg)
+    c = (np.arange(32) + 0.5) * 0.8 - 12.8
+    inside = (c >= -10.0) & (c < 10.0)   # half-open voxel intervals: x = -10 is inside
+    expect = np.where(inside[:, None] & inside[None, :], 20.0, 0.0)
+    assert np.allclose(t, expect, rtol=0, atol=1e-12)
+
+
+def test_thickness_point_source_oblique_slabs(orc):
+    """A point source over z slabs of different density: a ray that crosses the top and the
+    bottom face travels each slab's thickness over cos(theta)."""
+    slabs = [(1.0, 1.0)] * 5 + [(0.3, 1.0)] * 7 + [(1.85, 1.0)] * 3 + [(0.0012, 1.0)] * 2 + [(1.0, 1.0)] * 4
+    cfg = slab_case(slabs)
+    t = orc.radiological_thickness(cfg)
+    zmid = 150.0 + 0.2 + 0.02
+    c = (np.arange(24) + 0.5) * 1.0 - 12.0
+    x, y = np.meshgrid(c, c)   # [v, u]
+    cos_t = zmid / np.sqrt(x * x + y * y + zmid * zmid)
+    expect = sum(r * h for r, h in slabs) / cos_t
+    # all rays of this image stay inside the 40 cm wide slabs between z = 80 and 101
+    assert np.all(np.abs(x) * 101 / zmid < 20) and np.all(np.abs(y) * 101 / zmid < 20)
+    assert np.allclose(t, expect, rtol=1e-12, atol=0)
+
+
+def riemann(cfg, S, T, n=400_000):
+    """Midpoint sum of the density along S -> T at n points (brute force)."""
+    P = cfg["phantom"]
+    nx, ny, nz = P["shape"]
+    sp, o = np.array(P["spacing"], float), np.array(P["origin"], float)
+    rho = np.asarray(P["rho"], float).reshape(nz, ny, nx)
+    a = (np.arange(n) + 0.5) / n
+    pts = S[None, :] + a[:, None] * (T - S)[None, :]
+    idx = np.floor((pts - o) / sp).astype(np.int64)
+    ok = np.all((idx >= 0) & (idx < np.array([nx, ny, nz])), axis=1)
+    vals = np.zeros(n)
+    vals[ok] = rho[idx[ok, 2], idx[ok, 1], idx[ok, 0]]
+    return vals.sum() * np.linalg.norm(T - S) / n
+
+
+def test_thickness_brute_force_heterogeneous(orc):
+    """A random 5 x 4 x 3 grid of unequal spacing under an off-axis point source, against a
+    400 000-point midpoint sum along each ray."""
+    rng = np.random.default_rng(11)
+    cfg = synth.kerma_water(npx=6, pitch=4.0)
+    cfg["phantom"] = {"kind": "direct", "shape": (5, 4, 3), "spacing": (3.0, 4.5, 6.0), "origin": (-6.0, -8.0, 70.0),
+                      "mat": np.zeros(60, np.uint8), "rho": rng.uniform(0.0, 2.0, 60)}
+    cfg["epid"]["front_z"] = 140.0
+    cfg["source"]["beam"] = {"kind": 1, "src": (3.0, -2.0, 0.0), "iso_z": 100.0}
+    t = orc.radiological_thickness(cfg)
+    L = cfg["epid"]["layers"]
+    zmid = 140.0 + sum(l["t"] for l in L[:cfg["epid"]["scoring"]]) + 0.5 * L[cfg["epid"]["scoring"]]["t"]
+    S = np.array([3.0, -2.0, 0.0])
+    c = (np.arange(6) + 0.5) * 4.0 - 12.0
+    hit = 0
+    for v in range(6):
+        for u in range(6):
+            ref = riemann(cfg, S, np.array([c[u], c[v], zmid]))
+            hit += ref > 0
+            assert abs(t[v, u] - ref) < 2e-4 * max(1.0, ref), (u, v, t[v, u], ref)
+    assert hit >= 10   # most rays cross the grid
+
+
+def test_thickness_rays_missing_the_box(orc):
+    """Pixels whose rays pass beside the phantom see nothing."""
+    cfg = slab_case([(1.0, 1.0)] * 4, xy=4.0, npx=40, pitch=2.0)
+    t = orc.radiological_thickness(cfg)
+    assert t[0, 0] == 0.0 and t[-1, -1] == 0.0 and t[0, -1] == 0.0
+    assert abs(t[20, 20] - 4.0) < 0.01   # the central ray sees all four slabs (cos ~ 1)
+
+
+def aperture(segments, n_pairs=60, leaf_w=0.5):
+    """Segments as lists of (first pair, last pair, x0, x1): open [x0, x1) on those pairs."""
+    a = np.zeros((len(segments), n_pairs))
+    b = np.zeros((len(segments), n_pairs))
+    for s, opens in enumerate(segments):
+        for k0, k1, x0, x1 in opens:
+            a[s, k0:k1 + 1], b[s, k0:k1 + 1] = x0, x1
+    return {"a": a, "b": b, "leaf_w": leaf_w, "y0": -0.5 * n_pairs * leaf_w,
+            "counts": np.full(len(segments), 1000, np.uint64)}
+
+
+@pytest.mark.parametrize("segments,A,P", [
+    ([[(20, 39, -5.0, 5.0)]], 100.0, 40.0),                            # 10 x 10 square
+    ([[(10, 49, -5.0, 5.0)]], 200.0, 60.0),                            # 10 x 20
+    ([[(20, 23, -7.0, -3.0)], [(40, 43, 1.0, 9.0)]], 16 * 12.0, 2 * (16 + 12.0)),   # bounding box of a union
+])
+def test_equivalent_square_is_four_area_over_perimeter(orc, segments, A, P):
+    cfg = synth.kerma_water()
+    cfg["source"]["aperture"] = aperture(segments)
+    s = orc.equivalent_square(cfg)
+    assert abs(s - 4.0 * A / P) < 1e-12
+    # the square of side s has the rectangle's area-to-perimeter ratio
+    assert abs(s * s / (4 * s) - A / P) < 1e-12
+
+
+def test_response_factor_reproduces_table1_at_its_nodes(orc):
+    t, s, k = golden_table1()
+    ts, ss, ks = synth.response_table_1()
+    assert np.array_equal(t, ts) and np.array_equal(s, ss) and np.array_equal(k, ks)
+    for j in range(len(s)):
+        for i in range(len(t)):
+            assert orc.response_factor(ts, ss, ks, t[i], s[j]) == k[j, i]
+
+
+def test_response_factor_bilinear_between_nodes_and_clamped_outside(orc):
+    t, s, k = golden_table1()
+    for j in range(len(s) - 1):
+        for i in range(len(t) - 1):
+            mid = orc.response_factor(t, s, k, 0.5 * (t[i] + t[i + 1]), 0.5 * (s[j] + s[j + 1]))
+            assert abs(mid - 0.25 * (k[j, i] + k[j, i + 1] + k[j + 1, i] + k[j + 1, i + 1])) < 1e-15
+            q = orc.response_factor(t, s, k, t[i] + 0.25 * (t[i + 1] - t[i]), s[j])
+            assert abs(q - (0.75 * k[j, i] + 0.25 * k[j, i + 1])) < 1e-15
+    # clamped outside: beyond 20 cm of thickness, below a 5 cm and above a 20 cm field
+    assert orc.response_factor(t, s, k, 35.0, 10.0) == k[1, -1]
+    assert orc.response_factor(t, s, k, -2.0, 10.0) == k[1, 0]
+    assert orc.response_factor(t, s, k, 10.0, 2.0) == k[0, 2]
+    assert orc.response_factor(t, s, k, 10.0, 25.0) == k[-1, 2]
+    assert orc.response_factor(t, s, k, 40.0, 2.0) == k[0, -1]
