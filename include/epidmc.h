@@ -229,6 +229,31 @@ epidmc_status epidmc_reset_tally(epidmc_ctx *c, void *stream);
 /* Work and diagnostic counters accumulated since the last reset (synchronises). */
 epidmc_status epidmc_get_counters(epidmc_ctx *c, epidmc_counters *out);
 
+/* ---- dose-response correction (Sec. 2.2, Sec. 3.1) ---------------------------- */
+/* Radiological thickness map (Sec. 2.2, item 1): for every pixel, the line integral of the
+ * phantom's density divided by 1 g/cm^3 (cm) along the ray from the point source to the
+ * pixel centre on the mid-plane of the scoring layer, or along +z through the pixel centre
+ * for a parallel beam.  dev_out: device pointer to npx_u * npx_v doubles, row-major with u
+ * fastest (the image layout).  Needs a bound workspace, whose packed phantom it reads
+ * (densities within 2^-21 relative).  Runs on `stream` and returns without waiting.
+ * EPIDMC_E_NOT_READY if unbound, EPIDMC_E_ARG for a null pointer. */
+epidmc_status epidmc_radiological_thickness(epidmc_ctx *c, double *dev_out, void *stream);
+/* Effective field size (Sec. 2.2, item 2; Eq. 1 read as 4A/P), in cm: the equivalent
+ * square 2ab/(a+b) of the a x b bounding rectangle of the open leaf pairs (b > a) of all
+ * segments, on the aperture plane.  Host computation, no device work.  EPIDMC_E_NOT_READY
+ * without an aperture (a phase-space source) or with every leaf pair closed. */
+epidmc_status epidmc_field_size(epidmc_ctx *c, double *s_out);
+/* Dose-response correction (Sec. 3.1, Eq. 2 and Table 1): dev_out[p] = k(dev_t[p], s) *
+ * dev_image[p] for the npx_u * npx_v pixels.  k is bilinear on the rectilinear table
+ * t_nodes[nt], s_nodes[ns] (strictly ascending), k[j*nt + i] the factor at (t_i, s_j),
+ * 1 <= nt, ns <= 64, in host memory; outside the table t and s are clamped to its edges.
+ * dev_image, dev_t and dev_out are device pointers to doubles (dev_out may equal
+ * dev_image).  Runs on `stream` and returns without waiting.  EPIDMC_E_ARG / E_RANGE for
+ * bad pointers, sizes, unordered nodes or non-finite values. */
+epidmc_status epidmc_dose_response(epidmc_ctx *c, const double *dev_image, const double *dev_t, double s,
+                                   const double *t_nodes, int nt, const double *s_nodes, int ns,
+                                   const double *k, double *dev_out, void *stream);
+
 /* ---- diagnostics of the device building blocks (test entry points) ----------- */
 /* Philox4x32-10 on the device: out[4*i..4*i+3] = philox(ctr[4*i..], key).  Device pointers. */
 epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *dev_ctr, uint32_t *dev_out, uint64_t n,

@@ -77,8 +77,9 @@ EXPORTS = [
     "epidmc_set_source_phsp", "epidmc_set_segments", "epidmc_set_tally", "epidmc_set_diagnostics",
     "epidmc_set_profiling",
     "epidmc_workspace_size", "epidmc_bind_workspace", "epidmc_run", "epidmc_run_until", "epidmc_read_image",
-    "epidmc_sigma_bar", "epidmc_reset_tally", "epidmc_get_counters", "epidmc_debug_philox",
-    "epidmc_debug_sample", "epidmc_debug_table",
+    "epidmc_sigma_bar", "epidmc_reset_tally", "epidmc_get_counters",
+    "epidmc_radiological_thickness", "epidmc_field_size", "epidmc_dose_response",
+    "epidmc_debug_philox", "epidmc_debug_sample", "epidmc_debug_table",
 ]
 
 _lib = None
@@ -115,6 +116,9 @@ def load_library(path: str = LIB_PATH):
         "epidmc_sigma_bar": [vp, f64, vp, ct.POINTER(f64)],
         "epidmc_reset_tally": [vp, vp],
         "epidmc_get_counters": [vp, ct.POINTER(Counters)],
+        "epidmc_radiological_thickness": [vp, vp, vp],
+        "epidmc_field_size": [vp, ct.POINTER(f64)],
+        "epidmc_dose_response": [vp, vp, vp, f64, vp, i32, vp, i32, vp, vp, vp],
         "epidmc_debug_philox": [vp, vp, vp, u64, vp],
         "epidmc_debug_sample": [vp, i32, f64, f64, f64, vp, u64, vp],
         "epidmc_debug_table": [vp, i32, i32, vp, vp, u64, vp],
@@ -287,6 +291,34 @@ class Engine:
         self._check(self.L.epidmc_read_image(self.h, ct.c_void_p(mean.data_ptr()), ct.c_void_p(var.data_ptr()),
                                              self._stream()))
         return mean, var
+
+    def radiological_thickness(self):
+        """Per-pixel radiological thickness (cm), a float64 device tensor of the image shape."""
+        out = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device)
+        self._check(self.L.epidmc_radiological_thickness(self.h, ct.c_void_p(out.data_ptr()), self._stream()))
+        return out
+
+    def field_size(self):
+        out = ct.c_double()
+        self._check(self.L.epidmc_field_size(self.h, ct.byref(out)))
+        return out.value
+
+    def dose_response(self, image, thickness, s, t_nodes, s_nodes, k):
+        """k(thickness, s) * image on the device, k bilinear on the table k[s_j][t_i]."""
+        t = self.torch
+        img = image.to(device=self.device, dtype=t.float64).contiguous()
+        th = thickness.to(device=self.device, dtype=t.float64).contiguous()
+        npix = self.shape[0] * self.shape[1]
+        if img.numel() != npix or th.numel() != npix:
+            raise ValueError(f"image and thickness need {npix} pixels, got {img.numel()} and {th.numel()}")
+        out = t.empty_like(img)
+        tn = np.ascontiguousarray(t_nodes, dtype=np.float64)
+        sn = np.ascontiguousarray(s_nodes, dtype=np.float64)
+        kk = np.ascontiguousarray(k, dtype=np.float64)
+        self._check(self.L.epidmc_dose_response(self.h, ct.c_void_p(img.data_ptr()), ct.c_void_p(th.data_ptr()),
+                                                float(s), tn.ctypes.data, tn.size, sn.ctypes.data, sn.size,
+                                                kk.ctypes.data, ct.c_void_p(out.data_ptr()), self._stream()))
+        return out
 
     def sigma_bar(self, thr=0.5):
         out = ct.c_double()

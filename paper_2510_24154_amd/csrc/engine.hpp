@@ -149,6 +149,31 @@ struct Params {
     uint32_t key0, key1;
 };
 
+// arguments of the radiological-thickness kernel (global frame, cm)
+struct RadArgs {
+    double sx, sy, sz;      // point source
+    double zt;              // plane of the pixel centres: the scoring layer's mid-plane
+    int parallel;           // 1: rays along +z through the pixel centres
+    double hx, hy, pu, pv;  // image half extents and pitches
+    int npx_u, npx_v;
+    double ox, oy, oz;      // phantom minimum corner
+    double dx, dy, dz;      // voxel spacing
+    int nx, ny, nz;
+    const uint32_t *vox;    // packed voxels (density bits | material slot)
+    double *out;            // [npx_v][npx_u] cm
+};
+
+// arguments of the dose-response kernel: the k table at the field's s, as a function of t
+constexpr int RESP_MAX = 64;
+struct RespArgs {
+    int nt;
+    double tn[RESP_MAX];    // thickness nodes, ascending
+    double row[RESP_MAX];   // k(t_i, s)
+    const double *img, *t;
+    double *out;
+    uint32_t n;
+};
+
 enum Stat {
     S_COMPTON = 0, S_PHOTO, S_PAIR, S_ANNIH, S_BREMS, S_MOLLER,
     S_WOODCOCK, S_EPID_PH_STEPS, S_ESTEP_P, S_ESTEP_E, S_EPID_ENTRIES, S_UNSCAT,

@@ -26,6 +26,8 @@ hipError_t launch_sigma_bar(const Params &P, double n, double nb, double thr, do
 hipError_t launch_diag_check(const Params &P, uint32_t nh, unsigned long long *maxbits, double *sums, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_seg_total(const Params &P, const uint32_t *cnt, uint32_t *tot, hipStream_t s);
+hipError_t launch_radthick(const RadArgs &A, hipStream_t s);
+hipError_t launch_response(const RespArgs &A, hipStream_t s);
 hipError_t launch_dbg_philox(const Params &P, const uint32_t *ctr, uint32_t *out, unsigned long long n, hipStream_t s);
 hipError_t launch_dbg_sample(const Params &P, int kind, float p0, float p1, float p2, float *out,
                              unsigned long long n, hipStream_t s);
@@ -1029,6 +1031,88 @@ extern "C" epidmc_status epidmc_get_counters(epidmc_ctx *c, epidmc_counters *out
         o.kernel_launches[k] = c->kernel_launches[k];
     }
     return check_error_word(c, err);
+}
+
+extern "C" epidmc_status epidmc_radiological_thickness(epidmc_ctx *c, double *dev_out, void *stream)
+{
+    if (!c || !dev_out) return fail(c, EPIDMC_E_ARG, "null argument");
+    REQUIRE(c->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    RadArgs A{};
+    A.parallel = c->beam.kind == 0;
+    A.sx = c->beam.src[0]; A.sy = c->beam.src[1]; A.sz = c->beam.src[2];
+    double z = c->front_z;
+    for (int l = 0; l < c->scoring; ++l) z += (double)c->layers[l].thickness;
+    A.zt = z + 0.5 * (double)c->layers[c->scoring].thickness;
+    A.pu = c->pitch_u; A.pv = c->pitch_v;
+    A.hx = 0.5 * c->npx_u * A.pu; A.hy = 0.5 * c->npx_v * A.pv;
+    A.npx_u = c->npx_u; A.npx_v = c->npx_v;
+    A.ox = c->origin[0]; A.oy = c->origin[1]; A.oz = c->origin[2];
+    A.dx = c->spacing[0]; A.dy = c->spacing[1]; A.dz = c->spacing[2];
+    A.nx = c->nx; A.ny = c->ny; A.nz = c->nz;
+    A.vox = c->P.vox;
+    A.out = dev_out;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(launch_radthick(A, (hipStream_t)stream));
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_field_size(epidmc_ctx *c, double *s_out)
+{
+    if (!c || !s_out) return fail(c, EPIDMC_E_ARG, "null argument");
+    REQUIRE(c->n_phsp == 0 && c->n_seg > 0, EPIDMC_E_NOT_READY, "no aperture: set_segments first");
+    double xmin = INFINITY, xmax = -INFINITY;
+    int kmin = -1, kmax = -1;
+    for (int g = 0; g < c->n_seg; ++g)
+        for (int k = 0; k < c->n_pairs; ++k) {
+            const double a = c->ap_a[(size_t)g * c->n_pairs + k], b = c->ap_b[(size_t)g * c->n_pairs + k];
+            if (!(b > a)) continue;   // a closed pair
+            xmin = std::min(xmin, a);
+            xmax = std::max(xmax, b);
+            if (kmin < 0 || k < kmin) kmin = k;
+            kmax = std::max(kmax, k);
+        }
+    REQUIRE(kmin >= 0, EPIDMC_E_NOT_READY, "every leaf pair is closed");
+    const double A = xmax - xmin, B = (kmax + 1 - kmin) * (double)c->leaf_w;
+    *s_out = 2.0 * A * B / (A + B);
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_dose_response(epidmc_ctx *c, const double *dev_image, const double *dev_t, double s,
+                                              const double *t_nodes, int nt, const double *s_nodes, int ns,
+                                              const double *k, double *dev_out, void *stream)
+{
+    if (!c || !dev_image || !dev_t || !dev_out || !t_nodes || !s_nodes || !k) return fail(c, EPIDMC_E_ARG, "null argument");
+    REQUIRE(nt >= 1 && nt <= RESP_MAX && ns >= 1 && ns <= RESP_MAX, EPIDMC_E_RANGE, "table of 1..64 nodes per axis");
+    REQUIRE(std::isfinite(s), EPIDMC_E_RANGE, "field size not finite");
+    REQUIRE(c->npx_u > 0 && c->npx_v > 0, EPIDMC_E_NOT_READY, "no EPID image configured");
+    for (int i = 0; i < nt; ++i) REQUIRE(std::isfinite(t_nodes[i]) && (i == 0 || t_nodes[i] > t_nodes[i - 1]), EPIDMC_E_RANGE, "t nodes must ascend");
+    for (int j = 0; j < ns; ++j) REQUIRE(std::isfinite(s_nodes[j]) && (j == 0 || s_nodes[j] > s_nodes[j - 1]), EPIDMC_E_RANGE, "s nodes must ascend");
+    for (int q = 0; q < nt * ns; ++q) REQUIRE(std::isfinite(k[q]), EPIDMC_E_RANGE, "table values must be finite");
+    // the two rows bracketing s (clamped), blended: bilinear with s fixed is linear in t on it
+    int j = 0;
+    double fs = 0.0;
+    if (ns > 1 && s > s_nodes[0]) {
+        if (s >= s_nodes[ns - 1]) {
+            j = ns - 2; fs = 1.0;
+        } else {
+            while (j + 1 < ns - 1 && s >= s_nodes[j + 1]) ++j;
+            fs = (s - s_nodes[j]) / (s_nodes[j + 1] - s_nodes[j]);
+        }
+    }
+    const int j1 = ns > 1 ? j + 1 : j;
+    RespArgs A{};
+    A.nt = nt;
+    for (int i = 0; i < nt; ++i) {
+        A.tn[i] = t_nodes[i];
+        A.row[i] = (1.0 - fs) * k[j * nt + i] + fs * k[j1 * nt + i];
+    }
+    A.img = dev_image;
+    A.t = dev_t;
+    A.out = dev_out;
+    A.n = (uint32_t)c->npx_u * (uint32_t)c->npx_v;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(launch_response(A, (hipStream_t)stream));
+    return EPIDMC_OK;
 }
 
 extern "C" epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *ctr, uint32_t *out, uint64_t n, void *stream)

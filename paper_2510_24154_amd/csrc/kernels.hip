@@ -1109,6 +1109,113 @@ __global__ void k_zero_u64(unsigned long long *a, size_t n)
 }
 
 // ---------------------------------------------------------------------------------
+// dose-response correction (Sec. 2.2, Sec. 3.1)
+// ---------------------------------------------------------------------------------
+// Radiological thickness of the phantom along each pixel's ray (Sec. 2.2, item 1): the line
+// integral of the density over 1 g/cm^3, from the point source to the pixel centre on the
+// scoring layer's mid-plane (or along +z through the centre for a parallel beam).  One thread
+// per pixel walks the voxels with the incremental Amanatides-Woo traversal in FP64; the 64
+// rays of a wave are 64 neighbouring pixels of a row, so they cross nearly the same voxels.
+__global__ __launch_bounds__(256) void k_radthick(RadArgs A)
+{
+    const uint32_t pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= (uint32_t)A.npx_u * (uint32_t)A.npx_v) return;
+    const uint32_t u = pix % (uint32_t)A.npx_u, v = pix / (uint32_t)A.npx_u;
+    const double x = -A.hx + (u + 0.5) * A.pu, y = -A.hy + (v + 0.5) * A.pv;
+    // the segment S -> T in the phantom's frame (minimum corner at the origin)
+    double S[3], d[3];
+    if (A.parallel) {
+        S[0] = x - A.ox; S[1] = y - A.oy; S[2] = -1.0;
+        d[0] = 0.0; d[1] = 0.0; d[2] = A.nz * A.dz + 2.0;
+    } else {
+        S[0] = A.sx - A.ox; S[1] = A.sy - A.oy; S[2] = A.sz - A.oz;
+        d[0] = x - A.sx; d[1] = y - A.sy; d[2] = A.zt - A.sz;
+    }
+    const int n[3] = {A.nx, A.ny, A.nz};
+    const double h[3] = {A.dx, A.dy, A.dz};
+    double amin = 0.0, amax = 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double hi = n[a] * h[a];
+        if (d[a] == 0.0) {
+            if (S[a] < 0.0 || S[a] >= hi) amax = -1.0;   // parallel to the slab and outside it
+        } else {
+            double a1 = -S[a] / d[a], a2 = (hi - S[a]) / d[a];
+            if (a1 > a2) { const double t = a1; a1 = a2; a2 = t; }
+            amin = fmax(amin, a1);
+            amax = fmin(amax, a2);
+        }
+    }
+    double sum = 0.0;
+    if (amax > amin) {
+        // the voxel at the entry point, and per axis the parameter of the next plane crossing
+        int i[3], step[3];
+        double tmax[3], tdel[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double e = S[a] + amin * d[a];
+            i[a] = min(max((int)floor(e / h[a]), 0), n[a] - 1);
+            step[a] = d[a] > 0.0 ? 1 : (d[a] < 0.0 ? -1 : 0);
+            if (step[a] != 0) {
+                tmax[a] = ((i[a] + (step[a] > 0 ? 1 : 0)) * h[a] - S[a]) / d[a];
+                tdel[a] = h[a] / fabs(d[a]);
+            } else {
+                tmax[a] = INFINITY;
+                tdel[a] = INFINITY;
+            }
+        }
+        double al = amin;
+        const int limit = A.nx + A.ny + A.nz + 3;   // a straight line crosses at most this many voxels
+        for (int it = 0; it < limit; ++it) {
+            const int a = tmax[0] <= tmax[1] ? (tmax[0] <= tmax[2] ? 0 : 2) : (tmax[1] <= tmax[2] ? 1 : 2);
+            const double next = fmin(tmax[a], amax);
+            if (next > al) {
+                const uint32_t word = A.vox[((uint32_t)i[2] * (uint32_t)A.ny + (uint32_t)i[1]) * (uint32_t)A.nx + (uint32_t)i[0]];
+                sum += (double)__uint_as_float(word & ~3u) * (next - al);
+                al = next;
+            }
+            if (al >= amax) break;
+            i[a] += step[a];
+            if (i[a] < 0 || i[a] >= n[a]) break;
+            tmax[a] += tdel[a];
+        }
+        sum *= sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    }
+    A.out[pix] = sum;   // g/cm^2 over 1 g/cm^3
+}
+
+// Dose-response correction (Sec. 3.1, Eq. 2): out = k(t, s) * image.  For one field s is
+// fixed, so the bilinear table lookup is a linear one in t on the two table rows that bracket
+// s, blended on the host; the nodes and the blended row are staged in LDS for the search.
+__global__ __launch_bounds__(256) void k_response(RespArgs A)
+{
+    __shared__ double tn[RESP_MAX], row[RESP_MAX];
+    if (threadIdx.x < (unsigned)A.nt) {
+        tn[threadIdx.x] = A.tn[threadIdx.x];
+        row[threadIdx.x] = A.row[threadIdx.x];
+    }
+    __syncthreads();
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.n) return;
+    const double t = A.t[p];
+    double k;
+    if (A.nt == 1 || t <= tn[0]) {
+        k = row[0];
+    } else if (t >= tn[A.nt - 1]) {
+        k = row[A.nt - 1];
+    } else {
+        int lo = 0, hi = A.nt - 1;   // tn[lo] <= t < tn[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tn[mid] <= t) lo = mid; else hi = mid;
+        }
+        const double f = (t - tn[lo]) / (tn[hi] - tn[lo]);
+        k = (1.0 - f) * row[lo] + f * row[hi];
+    }
+    A.out[p] = k * A.img[p];
+}
+
+// ---------------------------------------------------------------------------------
 // building-block probes
 // ---------------------------------------------------------------------------------
 __global__ void k_dbg_philox(Params P, const uint32_t *ctr, uint32_t *out, unsigned long long n)
@@ -1293,6 +1400,19 @@ hipError_t launch_sigma_bar(const Params &P, double n, double nb, double thr, do
 hipError_t launch_diag_check(const Params &P, uint32_t nh, unsigned long long *maxbits, double *sums, hipStream_t s)
 {
     hipLaunchKernelGGL(k_diag_check, dim3(min(grid_for(nh, 256), 2048u)), dim3(256), 0, s, P, nh, maxbits, sums);
+    return hipGetLastError();
+}
+
+hipError_t launch_radthick(const RadArgs &A, hipStream_t s)
+{
+    const unsigned n = (unsigned)A.npx_u * (unsigned)A.npx_v;
+    hipLaunchKernelGGL(k_radthick, dim3((n + 255) / 256), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_response(const RespArgs &A, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_response, dim3((A.n + 255) / 256), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
