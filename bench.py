@@ -43,12 +43,12 @@ def kernel_source_sha():
 
 
 def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summaries
+    """HBM bytes per unit of work of `kernel` from the committed rocprofv3 counter summaries
     (FETCH_SIZE and WRITE_SIZE passes, calibrated on a plain copy), or None when no summary
     was taken on the current kernel sources."""
     import glob
     sha = kernel_source_sha()
-    key = f"traffic_bytes_per_launch[{kernel}]"
+    key = f"traffic_bytes_per_unit[{kernel}]"
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         kv = {}
         for line in open(f):
@@ -118,7 +118,8 @@ def main():
     ops_per_launch = units[dom] * per[dom] / launches
     achieved = ops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
     kname = KERNEL[dom]
-    traffic, tsrc = profiled_traffic(kname)
+    per_unit, tsrc = profiled_traffic(kname)
+    traffic = per_unit * units[dom] / launches if per_unit else None
     roof = {"bound": "alu", "kernel": kname,
             "achieved": round(achieved, 3), "peak": round(ALU_PEAK_OPS / 1e12, 3), "unit": "Tlane-op/s",
             "frac": round(achieved * 1e12 / ALU_PEAK_OPS, 4),
@@ -129,6 +130,31 @@ def main():
             "unit_of_work": "electron condensed-history step" if dom in (1, 3) else KIND[dom],
             "units_per_launch": round(units[dom] / launches), "ops_per_unit": per[dom],
             "lane_utilisation": round(c["lane_iters"][dom] / max(1, c["wave_iters"][dom]), 4)}
+
+    # the dose-response correction of the image (Sec. 2.2 and 3.1): radiological-thickness map,
+    # field size and k(t, s) from Table 1, timed with HIP events on the engine's stream
+    t_nodes, s_nodes, ktab = synth.response_table_1()
+    s_eq = eng.field_size()
+    img, _ = eng.image()
+    th = eng.radiological_thickness()
+    eng.dose_response(img, th, s_eq, t_nodes, s_nodes, ktab)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(reps):
+        th = eng.radiological_thickness()
+    e1.record()
+    for _ in range(reps):
+        corrected = eng.dose_response(img, th, s_eq, t_nodes, s_nodes, ktab)
+    e2.record()
+    torch.cuda.synchronize()
+    npix = img.numel()
+    rt_ms, kr_ms = e0.elapsed_time(e1) / reps, e1.elapsed_time(e2) / reps
+    response = {"field_size_cm": round(s_eq, 4), "rays": npix, "radiological_thickness_ms": round(rt_ms, 4),
+                "rays_per_s": round(npix / (rt_ms * 1e-3), 1), "k_correction_ms": round(kr_ms, 4),
+                "thickness_cm_range": [round(float(th.min()), 3), round(float(th.max()), 3)],
+                "corrected_over_plain": round(float(corrected.sum() / img.sum()), 5)}
 
     if a.calib_copy:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -176,6 +202,7 @@ def main():
         "N_for_sigma_bar": n,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "dose_response": response,
         "counters": {k: c[k] for k in ("woodcock_steps", "e_steps_phantom", "e_steps_epid", "epid_photon_steps",
                                        "tally_deposits", "launches", "kernel_ms", "kernel_launches",
                                        "queue_items", "lane_iters", "wave_iters")},
