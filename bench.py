@@ -42,22 +42,35 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel):
+def profiled_traffic(kernel, workload):
     """HBM bytes per unit of work of `kernel` from the committed rocprofv3 counter summaries
     (FETCH_SIZE and WRITE_SIZE passes, calibrated on a plain copy), or None when no summary
     was taken on the current kernel sources."""
     import glob
     sha = kernel_source_sha()
     key = f"traffic_bytes_per_unit[{kernel}]"
+    wl = workload
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         kv = {}
         for line in open(f):
             parts = line.strip().split(": ", 1)
             if len(parts) == 2:
                 kv[parts[0]] = parts[1]
-        if kv.get("source_sha") == sha and key in kv:
+        if kv.get("source_sha") == sha and kv.get("workload") == wl and key in kv:
             return float(kv[key]), os.path.basename(f)
     return None, None
+
+
+# workloads: the default benchmark line is "coupled"; the two segmented fields deliver the
+# whole field (history ids [0, total)) in every step
+WORKLOADS = {
+    "coupled": ("coupled 6MV-like spectrum, 256x256x128 HU phantom (water/lung/bone), "
+                "4-layer EPID 1024x768 @0.39 mm, 1e8 histories per step", HISTORIES),
+    "imrt40": ("40-segment IMRT-like field (60 leaf pairs, uneven counts 1e6-5e7), same phantom and EPID "
+               "as coupled, 3e8 histories per step", 300_000_000),
+    "large60": ("60-segment field on a 512x512x200 anthropomorphic-like phantom of 1 mm voxels, "
+                "4-layer EPID 1024x768, 2e9 histories per step", 2_000_000_000),
+}
 
 
 def parse():
@@ -65,7 +78,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--histories", type=int, default=HISTORIES)
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="coupled")
+    ap.add_argument("--histories", type=int, default=None,
+                    help="histories per step (default: the workload's; a segmented field is rescaled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -85,28 +100,41 @@ def main():
     import paper_2510_24154_amd as E
     from paper_2510_24154_amd import synth
 
-    cfg = synth.coupled_hetero()
-    eng = E.Engine(0, seed=1).configure(cfg, batches=BATCHES, max_chunk=min(CHUNK, a.histories))
+    desc, n_default = WORKLOADS[a.workload]
+    n_step = a.histories or n_default
+    segmented = a.workload != "coupled"
+    if a.workload == "coupled":
+        cfg = synth.coupled_hetero()
+    elif a.workload == "imrt40":
+        cfg = synth.imrt_field()
+    else:
+        cfg = synth.large_anthropomorphic()
+    if segmented and n_step != n_default:
+        cfg = synth.with_histories_scaled(cfg, n_step)
+    eng = E.Engine(0, seed=1).configure(cfg, batches=BATCHES, max_chunk=min(CHUNK, n_step))
     eng.bind()
     eng.set_profiling(True)
     h = 0
     for _ in range(a.warmup):
-        eng.run(a.histories, first=h)
-        h += a.histories
+        eng.run(n_step, first=h)
+        h = 0 if segmented else h + n_step
     eng.reset()
     torch.cuda.synchronize()
     first = h
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        eng.run(a.histories, first=h)
-        h += a.histories
+    for i in range(a.steps):
+        if segmented and i > 0:
+            eng.reset()   # the same field again: sigma-bar and the counters describe one delivery
+        eng.run(n_step, first=h)
+        h = 0 if segmented else h + n_step
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    n = a.steps * a.histories
+    n = a.steps * n_step
     sb = eng.sigma_bar(0.5)
     c = eng.counters()
     value = n / dt
-    t1 = dt * (sb / 0.01) ** 2 if sb > 0 else None
+    # time to 1%: one delivery's sigma-bar scaled by 1/sqrt(N)
+    t1 = (dt / a.steps if segmented else dt) * (sb / 0.01) ** 2 if sb > 0 else None
 
     # roofline of the dominant kernel: algorithmic lane-ops per launch / average launch time
     units = {1: c["e_steps_phantom"], 0: c["woodcock_steps"], 2: c["epid_photon_steps"], 3: c["e_steps_epid"]}
@@ -118,7 +146,7 @@ def main():
     ops_per_launch = units[dom] * per[dom] / launches
     achieved = ops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
     kname = KERNEL[dom]
-    per_unit, tsrc = profiled_traffic(kname)
+    per_unit, tsrc = profiled_traffic(kname, a.workload)
     traffic = per_unit * units[dom] / launches if per_unit else None
     roof = {"bound": "alu", "kernel": kname,
             "achieved": round(achieved, 3), "peak": round(ALU_PEAK_OPS / 1e12, 3), "unit": "Tlane-op/s",
@@ -163,7 +191,7 @@ def main():
         torch.cuda.synchronize()
 
     cpu = None
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and a.workload == "coupled":
         import oracle
         threads = max(1, min(16, os.cpu_count() or 1))
         ns = a.cpu_sample
@@ -193,13 +221,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "coupled 6MV-like spectrum, 256x256x128 HU phantom (water/lung/bone), "
-                               "4-layer EPID 1024x768 @0.39 mm, 1e8 histories per step",
-                   "histories_per_step": a.histories, "batches": BATCHES, "tally": "fp64",
-                   "first_history": first},
+        "config": {"workload": desc, "name": a.workload,
+                   "histories_per_step": n_step, "batches": BATCHES, "tally": "fp64",
+                   "first_history": first, "chunk": min(CHUNK, n_step)},
         "s_to_1pct_extrapolated": round(t1, 2) if t1 else None,
         "sigma_bar_at_N": round(sb, 5),
-        "N_for_sigma_bar": n,
+        "N_for_sigma_bar": n_step if segmented else n,
         "roofline": roof,
         "cpu_baseline": cpu,
         "dose_response": response,

@@ -223,6 +223,53 @@ def with_histories_scaled(cfg, total):
     return cfg
 
 
+# --------------------------------------------------------------------------
+# workload 5: large anthropomorphic-like phantom under a 60-segment field
+# --------------------------------------------------------------------------
+def anthropomorphic_hu(shape=(512, 512, 200), spacing=0.1, iso_z=100.0):
+    """int16 HU grid (x fastest) of a thorax-like phantom for a beam along +z (anterior to
+    posterior): an elliptic cylinder of soft tissue (HU 40) along y, semi-axes 17 cm (x) and
+    9.5 cm (z), with a 3 mm skin shell (HU 60), a pair of lungs (HU -750; ellipsoids at
+    x = -/+8 cm, semi-axes 5.5 x 12 x 5.5 cm, 1 cm anterior of the centre) and a spine
+    (HU 800; a cylinder along y of radius 1.8 cm, 6 cm posterior of the centre); air
+    (HU -1000) outside."""
+    nx, ny, nz = shape
+    x = (np.arange(nx) + 0.5) * spacing - 0.5 * nx * spacing
+    y = (np.arange(ny) + 0.5) * spacing - 0.5 * ny * spacing
+    z = (np.arange(nz) + 0.5) * spacing - 0.5 * nz * spacing   # relative to the isocentre
+    X, Y, Z = x[None, None, :], y[None, :, None], z[:, None, None]
+    hu = np.full((nz, ny, nx), -1000, dtype=np.int16)
+    r_body = (X / 17.0) ** 2 + (Z / 9.5) ** 2                  # constant along y
+    body = np.broadcast_to(r_body <= 1.0, hu.shape)
+    hu[body] = 60
+    inner = np.broadcast_to((X / 16.7) ** 2 + (Z / 9.2) ** 2 <= 1.0, hu.shape)
+    hu[inner] = 40
+    for cx in (-8.0, 8.0):
+        lung = ((X - cx) / 5.5) ** 2 + (Y / 12.0) ** 2 + ((Z + 1.0) / 5.5) ** 2 <= 1.0
+        hu[lung] = -750
+    spine = np.broadcast_to(X ** 2 + (Z - 6.0) ** 2 <= 1.8 ** 2, hu.shape)
+    hu[spine] = 800
+    return hu.reshape(-1)
+
+
+def large_anthropomorphic(total=2_000_000_000, npx=(768, 1024), pitch=0.039):
+    """The large heterogeneous case: the anthropomorphic-like phantom on 512x512x200 voxels
+    of 1 mm (52 M voxels, 210 MB packed) centred on the isocentre, a 60-segment MLC field of
+    uneven history counts summing to `total`, the 6 MV-like spectrum and the 4-layer EPID of
+    the coupled workload."""
+    shape, sp = (512, 512, 200), (0.1, 0.1, 0.1)
+    cfg = coupled_hetero(shape=(8, 8, 8))   # everything but the phantom and the aperture
+    origin = (-0.5 * shape[0] * sp[0], -0.5 * shape[1] * sp[1], 100.0 - 0.5 * shape[2] * sp[2])
+    cfg["name"] = "large60"
+    cfg["phantom"] = {"kind": "hu", "shape": shape, "spacing": sp, "origin": origin,
+                      "hu": anthropomorphic_hu(shape, sp[0]),
+                      "curve": copy.deepcopy(HU_CURVE), "ranges": copy.deepcopy(HU_RANGES)}
+    cfg["epid"] = _epid(cfg["epid"]["layers"], 2, cfg["epid"]["front_z"], npx[0], npx[1], pitch)
+    cfg["source"]["aperture"] = mlc_segments(n_seg=60, total=total, aperture_seed=6, count_seed=7,
+                                             lo=total // 300, hi=total // 6)
+    return cfg
+
+
 def response_table_1():
     """The EPID dose-response correction factors k(t, s) the paper measured (Sec. 3.1, Eq. 2,
     Table 1): thickness nodes t (cm of solid water), field-side nodes s (cm), and k[j][i] at

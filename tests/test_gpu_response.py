@@ -146,3 +146,32 @@ def test_dose_response_rejects_bad_tables(E):
         eng.dose_response(z, z, 10.0, np.arange(65.0), s_nodes, np.ones((4, 65)))   # over 64 nodes
     with pytest.raises(E.EpidmcError):
         eng.dose_response(z, z, float("nan"), t_nodes, s_nodes, k)
+
+
+def test_radiological_thickness_large_phantom(E, orc):
+    """The large case: 512x512x200 voxels of 1 mm (52 M voxels, 210 MB packed, larger than one
+    XCD's L2 many times over), every pixel of the 1024x768 image against the oracle."""
+    cfg = synth.large_anthropomorphic(total=1_000_000)
+    eng = E.Engine(0, seed=1).configure(cfg, batches=16, max_chunk=1 << 20)
+    eng.bind()
+    dev = eng.radiological_thickness().cpu().numpy()
+    ref = orc.radiological_thickness(as_engine_sees_it(cfg))
+    print("large phantom radiological thickness range", ref.min(), ref.max())
+    assert ref.max() > 15.0   # rays cross the body
+    assert np.all(np.abs(dev - ref) <= TOL * ref + 1e-9)
+    # the field size of the 60-segment union matches as well
+    assert abs(eng.field_size() - orc.equivalent_square(as_engine_sees_it(cfg))) < 1e-6
+
+
+def test_large_case_transport_energy_ledger(E):
+    """Coupled transport through the large phantom under the 60-segment field (scaled to 2e5
+    histories): every history's ledger closes to 1e-9 on the device."""
+    cfg = synth.large_anthropomorphic(total=200_000)
+    eng = E.Engine(0, seed=3).configure(cfg, batches=16, max_chunk=1 << 17, diag=True)
+    eng.bind()
+    eng.run(200_000)
+    c = eng.counters()
+    print("large case: ledger", c["max_ledger_resid"], "woodcock steps/history", c["woodcock_steps"] / 2e5)
+    assert c["max_ledger_resid"] < 1e-9
+    m, v = eng.image()
+    assert bool(np.isfinite(m.cpu().numpy()).all()) and float(m.sum()) > 0
