@@ -265,24 +265,45 @@ __device__ __forceinline__ float kn_sample(const Params &P, Part &p, float E, fl
     return eps;
 }
 
-// Moller energy transfer W in [WCUT, T/2]: 1/eps^2 proposal, rejection by the rest of the
-// Moller bracket, bounded by 2 + c1/4 on the interval
+// Moller energy transfer W = eps T in [WCUT, T/2]: a 1/eps^2 proposal on [WCUT/T, 1/2] from
+// u1, accepted with u2 against the rest of the Moller bracket, which 2 + c1/4 bounds on the
+// interval
+struct MollerC {
+    float ec, c1, c2, bound;
+};
+
+__device__ __forceinline__ MollerC moller_setup(float T)
+{
+    MollerC m;
+    m.ec = (float)WCUT / T;
+    const float g = T * (1.0f / MEC2F) + 1.0f;
+    m.c1 = (g - 1.0f) * (g - 1.0f) / (g * g);
+    m.c2 = (2.0f * g - 1.0f) / (g * g);
+    m.bound = 2.0f + 0.25f * m.c1;
+    return m;
+}
+
+__device__ __forceinline__ bool moller_trial(const MollerC &m, float u1, float u2, float &eps)
+{
+    const float e = m.ec / (1.0f - u1 * (1.0f - 2.0f * m.ec));
+    const float x = e / (1.0f - e);
+    const float gf = 1.0f + x * x + m.c1 * e * e - m.c2 * x;
+    eps = fminf(fmaxf(e, m.ec), 0.5f);
+    return u2 * m.bound < gf;
+}
+
+// a complete Moller sample (one trial per Philox draw until accepted); also returns the
+// azimuth uniform of the accepted trial
 __device__ __forceinline__ float moller_sample(const Params &P, Part &p, float T, float &phi_u)
 {
-    const float ec = (float)WCUT / T;
-    const float g = T * (1.0f / MEC2F) + 1.0f;
-    const float c1 = (g - 1.0f) * (g - 1.0f) / (g * g), c2 = (2.0f * g - 1.0f) / (g * g);
-    const float bound = 2.0f + 0.25f * c1;
-    float eps = ec;
+    const MollerC m = moller_setup(T);
+    float eps = m.ec;
     for (int trial = 0; trial < 10000; ++trial) {
         const float4 r = rnd4(p, P);
-        eps = ec / (1.0f - r.x * (1.0f - 2.0f * ec));
-        const float x = eps / (1.0f - eps);
-        const float gf = 1.0f + x * x + c1 * eps * eps - c2 * x;
         phi_u = r.z;
-        if (r.y * bound < gf) break;
+        if (moller_trial(m, r.x, r.y, eps)) break;
     }
-    return fminf(fmaxf(eps, ec), 0.5f) * T;
+    return eps * T;
 }
 
 // Highland width (unit charge) for kinetic energy T over x g/cm^2 of radiation length X0
@@ -740,6 +761,8 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
     Local L;
     zero(L);
     int nsteps = 0;
+    int hpend = 0;   // a hard event pending at p: 1 process not chosen yet, 2 a Moller sample to retry
+    int hmat = 0;    // the medium of the step that ended in it
     unsigned long long lane_iters = 0, wave_iters = 0;
     for (;;) {
         stage_flush_all(P, S, SBUF_E / 2);
@@ -752,6 +775,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
         if (active && !was) {
             ++L.items;
             nsteps = 0;
+            hpend = 0;
             px = p.x; py = p.y; pz = p.z;
         }
         if (!active) continue;
@@ -761,134 +785,175 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
             active = false;
             continue;
         }
-        ++L.steps;
-        // current cell and medium
-        float rho, smin;
-        double lo0, hi0, lo1, hi1, lo2, hi2;
-        int m, layer = -1;
-        if (!EPID) {
-            const int ix = min(max((int)(px * P.iddx), 0), P.nx - 1);
-            const int iy = min(max((int)(py * P.iddy), 0), P.ny - 1);
-            const int iz = min(max((int)(pz * P.iddz), 0), P.nz - 1);
-            const uint32_t word = P.vox[((size_t)iz * P.ny + iy) * P.nx + ix];
-            rho = __uint_as_float(word & ~3u);
-            m = (int)(word & 3u);
-            lo0 = ix * P.ddx; hi0 = lo0 + P.ddx;
-            lo1 = iy * P.ddy; hi1 = lo1 + P.ddy;
-            lo2 = iz * P.ddz; hi2 = lo2 + P.ddz;
-            smin = P.smin_ph;
-        } else {
-            int l = 0;
-#pragma unroll
-            for (int k = 1; k < MAX_LAYERS; ++k)
-                if (k < P.nl && pz >= (double)s_zl[k]) l = k;
-            layer = l;
-            m = l;
-            rho = s_rho[l];
-            lo0 = -P.hx; hi0 = P.hx; lo1 = -P.hy; hi1 = P.hy;
-            lo2 = s_zl[l]; hi2 = s_zl[l + 1];
-            smin = s_smin[l];
-        }
-        // distance to the cell faces: the offset to the face is taken in FP64, then the small
-        // difference is divided in FP32
-        float dg = INFINITY;
-        if (p.u != 0.0f) dg = fminf(dg, (float)((p.u > 0.0f ? hi0 : lo0) - px) / p.u);
-        if (p.v != 0.0f) dg = fminf(dg, (float)((p.v > 0.0f ? hi1 : lo1) - py) / p.v);
-        if (p.w != 0.0f) dg = fminf(dg, (float)((p.w > 0.0f ? hi2 : lo2) - pz) / p.w);
-        const float sg = fmaxf(fmaxf(dg, 0.0f) + NUDGE, smin);
+        // One Philox draw per lane and iteration, spent together by the wave: a step uses it for
+        // the distance to a hard event, the hinge and the scattering angles; a pending hard event
+        // uses it to choose between Moller and bremsstrahlung and for a Moller trial.
+        const float4 r = rnd4(p, P);
         float T = p.E;
-        if (!(rho > 0.0f)) {
-            px += (double)sg * p.u;
-            py += (double)sg * p.v;
-            pz += (double)sg * p.w;
-        } else {
-            const float *tab = lds + m * 3 * NB_EL;
-            const float lnT = __logf(T);
-            const Node n0 = node_of(lnT, P.el_lnT0, P.el_idl, NB_EL);
-            const float R0 = lerp_tab(tab, n0);
-            const float sh = lerp_tab(tab + NB_EL, n0);
-            const Node n9 = node_of(lnT + ln09, P.el_lnT0, P.el_idl, NB_EL);
-            const float R9 = lerp_tab(tab, n9);
-            const float4 r = rnd4(p, P);
-            const float irho = 1.0f / rho;
-            const float s_hard = sh > 0.0f ? -__logf(r.x) / (rho * sh) : INFINITY;
-            const float s_de = (R0 - R9) * irho;
-            const float s_pix = (EPID && layer == P.scoring) ? P.s_pix : INFINITY;
-            const float s = fminf(fminf(s_hard, s_de), fminf(sg, s_pix));
-            const bool hard = s_hard <= fminf(s_de, fminf(sg, s_pix));
-            float T1;
-            if (s == s_de) {
-                T1 = DE_FRAC * T;
+        bool settle = false;   // the end-of-step checks: cut-off, leaving the region
+        bool emit = false;     // a secondary set in motion at p
+        uint32_t etype = 0u;
+        float eE = 0.0f, eu = 0.0f, ev = 0.0f, ew = 0.0f;
+        if (hpend == 0) {
+            ++L.steps;
+            // current cell and medium
+            float rho, smin;
+            double lo0, hi0, lo1, hi1, lo2, hi2;
+            int m, layer = -1;
+            if (!EPID) {
+                const int ix = min(max((int)(px * P.iddx), 0), P.nx - 1);
+                const int iy = min(max((int)(py * P.iddy), 0), P.ny - 1);
+                const int iz = min(max((int)(pz * P.iddz), 0), P.nz - 1);
+                const uint32_t word = P.vox[((uint32_t)iz * (uint32_t)P.ny + (uint32_t)iy) * (uint32_t)P.nx + (uint32_t)ix];
+                rho = __uint_as_float(word & ~3u);
+                m = (int)(word & 3u);
+                lo0 = ix * P.ddx; hi0 = lo0 + P.ddx;
+                lo1 = iy * P.ddy; hi1 = lo1 + P.ddy;
+                lo2 = iz * P.ddz; hi2 = lo2 + P.ddz;
+                smin = P.smin_ph;
             } else {
-                // invert the range table: find j with R[j] <= Rt < R[j+1] between the 0.9 T0 node and T0's
-                const float Rt = R0 - rho * s;
-                int lo = n9.i, hi = n0.i + 1;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (tab[mid] <= Rt) lo = mid; else hi = mid;
+                int l = 0;
+#pragma unroll
+                for (int k = 1; k < MAX_LAYERS; ++k)
+                    if (k < P.nl && pz >= (double)s_zl[k]) l = k;
+                layer = l;
+                m = l;
+                rho = s_rho[l];
+                lo0 = -P.hx; hi0 = P.hx; lo1 = -P.hy; hi1 = P.hy;
+                lo2 = s_zl[l]; hi2 = s_zl[l + 1];
+                smin = s_smin[l];
+            }
+            // distance to the cell faces: the offset to the face is taken in FP64, then the small
+            // difference is divided in FP32
+            float dg = INFINITY;
+            if (p.u != 0.0f) dg = fminf(dg, (float)((p.u > 0.0f ? hi0 : lo0) - px) / p.u);
+            if (p.v != 0.0f) dg = fminf(dg, (float)((p.v > 0.0f ? hi1 : lo1) - py) / p.v);
+            if (p.w != 0.0f) dg = fminf(dg, (float)((p.w > 0.0f ? hi2 : lo2) - pz) / p.w);
+            const float sg = fmaxf(fmaxf(dg, 0.0f) + NUDGE, smin);
+            settle = true;
+            if (!(rho > 0.0f)) {
+                px += (double)sg * p.u;
+                py += (double)sg * p.v;
+                pz += (double)sg * p.w;
+            } else {
+                const float *tab = lds + m * 3 * NB_EL;
+                const float lnT = __logf(T);
+                const Node n0 = node_of(lnT, P.el_lnT0, P.el_idl, NB_EL);
+                const float R0 = lerp_tab(tab, n0);
+                const float sh = lerp_tab(tab + NB_EL, n0);
+                const Node n9 = node_of(lnT + ln09, P.el_lnT0, P.el_idl, NB_EL);
+                const float R9 = lerp_tab(tab, n9);
+                const float s_hard = sh > 0.0f ? -__logf(r.x) / (rho * sh) : INFINITY;
+                const float s_de = (R0 - R9) / rho;
+                const float s_pix = (EPID && layer == P.scoring) ? P.s_pix : INFINITY;
+                const float s = fminf(fminf(s_hard, s_de), fminf(sg, s_pix));
+                const bool hard = s_hard <= fminf(s_de, fminf(sg, s_pix));
+                float T1;
+                if (s == s_de) {
+                    T1 = DE_FRAC * T;
+                } else {
+                    // invert the range table: find j with R[j] <= Rt < R[j+1] between the 0.9 T0 node and T0's
+                    const float Rt = R0 - rho * s;
+                    int lo = n9.i, hi = n0.i + 1;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (tab[mid] <= Rt) lo = mid; else hi = mid;
+                    }
+                    const float d = tab[lo + 1] - tab[lo];
+                    const float f = d > 0.0f ? fminf(fmaxf((Rt - tab[lo]) / d, 0.0f), 1.0f) : 0.0f;
+                    T1 = fminf(__expf(P.el_lnT0 + ((float)lo + f) / P.el_idl), T);
                 }
-                const float d = tab[lo + 1] - tab[lo];
-                const float f = d > 0.0f ? fminf(fmaxf((Rt - tab[lo]) / d, 0.0f), 1.0f) : 0.0f;
-                T1 = fminf(__expf(P.el_lnT0 + ((float)lo + f) / P.el_idl), T);
+                // hinge point: the step's continuous loss is deposited there
+                const double a = (double)(r.y * s);
+                px += a * p.u;
+                py += a * p.v;
+                pz += a * p.w;
+                const float dep = T - T1;
+                if (P.diag) ledger(P, p.hist, (double)T - (double)T1);
+                if (EPID && layer == P.scoring) {
+                    tally(P, p.flags, (float)px, (float)py, dep);
+                    ++L.tally;
+                }
+                if (!(P.mask & 16u)) {
+                    const float th = highland(T, rho * s, s_x0[(EPID ? MAX_PMAT : 0) + m]) * sqrtf(-2.0f * __logf(r.z));
+                    float sth, cth, sp, cp;
+                    __sincosf(th, &sth, &cth);
+                    __sincosf(TWO_PI_F * r.w, &sp, &cp);
+                    rotate(p.u, p.v, p.w, cth, sth, cp, sp);
+                }
+                const double bb = (double)s - a;
+                px += bb * p.u;
+                py += bb * p.v;
+                pz += bb * p.w;
+                T = T1;
+                p.E = T;
+                if (hard) {
+                    // the event itself takes the next draw, with the rest of the wave
+                    hpend = 1;
+                    hmat = m;
+                    settle = false;
+                }
             }
-            // hinge point: the step's continuous loss is deposited there
-            const double a = (double)(r.y * s);
-            px += a * p.u;
-            py += a * p.v;
-            pz += a * p.w;
-            const float dep = T - T1;
-            if (P.diag) ledger(P, p.hist, (double)T - (double)T1);
-            if (EPID && layer == P.scoring) {
-                tally(P, p.flags, (float)px, (float)py, dep);
-                ++L.tally;
-            }
-            if (!(P.mask & 16u)) {
-                const float th = highland(T, rho * s, s_x0[(EPID ? MAX_PMAT : 0) + m]) * sqrtf(-2.0f * __logf(r.z));
-                float sth, cth, sp, cp;
-                __sincosf(th, &sth, &cth);
-                __sincosf(TWO_PI_F * r.w, &sp, &cp);
-                rotate(p.u, p.v, p.w, cth, sth, cp, sp);
-            }
-            const double b = (double)s - a;
-            px += b * p.u;
-            py += b * p.v;
-            pz += b * p.w;
-            T = T1;
-            p.E = T;
-            if (hard) {
-                p.x = (float)px; p.y = (float)py; p.z = (float)pz;
+            p.x = (float)px; p.y = (float)py; p.z = (float)pz;
+        } else {
+            // the hard event at the end of the previous step (position p, energy T)
+            const float *tab = lds + hmat * 3 * NB_EL;
+            bool moller = hpend == 2;
+            float u1 = r.x, u2 = r.y, uphi = r.z;   // a retried Moller trial
+            if (hpend == 1) {
                 const Node n1 = node_of(__logf(T), P.el_lnT0, P.el_idl, NB_EL);
-                const float fm = lerp_tab(tab + 2 * NB_EL, n1);
-                const float4 r2 = rnd4(p, P);
-                if (r2.x < fm && T > 2.0f * (float)WCUT) {
-                    ++L.moller;
-                    float phu;
-                    const float W = moller_sample(P, p, T, phu);
-                    const float Tp = T - W;
+                moller = r.x < lerp_tab(tab + 2 * NB_EL, n1) && T > 2.0f * (float)WCUT;
+                if (moller) ++L.moller; else ++L.brems;
+                u1 = r.y; u2 = r.z; uphi = r.w;
+            }
+            if (moller) {
+                float eps;
+                if (moller_trial(moller_setup(T), u1, u2, eps)) {
+                    const float W = eps * T, Tp = T - W;
                     const float tt = T + 2.0f * MEC2F;
                     const float cd = fminf(1.0f, sqrtf(W * tt / (T * (W + 2.0f * MEC2F))));
                     const float cq = fminf(1.0f, sqrtf(Tp * tt / (T * (Tp + 2.0f * MEC2F))));
                     float sp, cp;
-                    __sincosf(TWO_PI_F * phu, &sp, &cp);
-                    float du = p.u, dv = p.v, dw = p.w;
-                    rotate(du, dv, dw, cd, sqrtf(fmaxf(0.0f, 1.0f - cd * cd)), cp, sp);
+                    __sincosf(TWO_PI_F * uphi, &sp, &cp);
+                    eu = p.u; ev = p.v; ew = p.w;
+                    rotate(eu, ev, ew, cd, sqrtf(fmaxf(0.0f, 1.0f - cd * cd)), cp, sp);
                     rotate(p.u, p.v, p.w, cq, sqrtf(fmaxf(0.0f, 1.0f - cq * cq)), -cp, -sp);
                     if (P.diag) ledger(P, p.hist, (double)T - (double)Tp - (double)W);
                     T = Tp;
-                    p.E = T;
-                    emit_electron(P, region, p, W, 1u, du, dv, dw, L, S);
+                    emit = true;
+                    etype = 1u;
+                    eE = W;
+                    hpend = 0;
+                    settle = true;
                 } else {
-                    ++L.brems;
-                    const float k = (float)KCUT * __expf(r2.y * __logf(T * (float)(1.0 / KCUT)));
-                    const float Tn = T - k;
-                    if (P.diag) ledger(P, p.hist, (double)T - (double)Tn - (double)k);
-                    T = Tn;
-                    p.E = T;
-                    emit_photon(P, region, p, k, p.u, p.v, p.w, L, S);
+                    hpend = 2;
                 }
+            } else {
+                const float k = (float)KCUT * __expf(u1 * __logf(T * (float)(1.0 / KCUT)));
+                const float Tn = T - k;
+                if (P.diag) ledger(P, p.hist, (double)T - (double)Tn - (double)k);
+                T = Tn;
+                emit = true;
+                etype = 0u;
+                eE = k;
+                eu = p.u; ev = p.v; ew = p.w;
+                hpend = 0;
+                settle = true;
             }
+            p.E = T;
         }
-        p.x = (float)px; p.y = (float)py; p.z = (float)pz;
+        if (emit) {
+            // the delta ray or bremsstrahlung photon, from one code path
+            Part c;
+            make_child(p, c, etype);
+            c.x = p.x; c.y = p.y; c.z = p.z;
+            c.u = eu; c.v = ev; c.w = ew;
+            c.E = eE;
+            const bool local = etype == 0u ? eE < P.pcut : (!P.coupled || eE < P.ecut);
+            if (local) deposit_point(P, region, c, eE, L);
+            else place(P, region, c, L, S);
+        }
+        if (!settle) continue;
         if (T < P.ecut) {
             deposit_point(P, region, p, T, L);
             if ((p.flags & F_TYPE) == 2u) annihilate(P, region, p, L, S);
@@ -900,11 +965,11 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
             const bool inside = px >= 0.0 && px < (double)P.Lx && py >= 0.0 && py < (double)P.Ly && pz >= 0.0 &&
                                 pz < (double)P.Lz;
             if (!inside) {
-                const int r = vacuum_phantom_frame(P, p);
-                if (r == 0) {
+                const int rr = vacuum_phantom_frame(P, p);
+                if (rr == 0) {
                     px = p.x; py = p.y; pz = p.z;   // re-entered through a face
                 } else {
-                    if (r == 1) append(P, S, QEE, true, p);
+                    if (rr == 1) append(P, S, QEE, true, p);
                     else ledger(P, p.hist, (double)p.E);
                     active = false;
                 }
