@@ -320,42 +320,30 @@ __device__ __forceinline__ float highland(float T, float x, float X0)
 }
 
 // ---------------------------------------------------------------------------------
-// photon interactions.  Each returns true while the photon lives.
+// photon interactions (the photon kernels inline the common Compton and photoelectric paths)
 // ---------------------------------------------------------------------------------
-// Compton kinematics after a Klein-Nishina sample (eps = E'/E, t = 1 - cos theta, azimuth
-// uniform phu): the photon turns and keeps eps E; the electron takes the rest, in the
-// direction that conserves momentum, on the opposite azimuth.
-__device__ __forceinline__ bool compton_finish(const Params &P, int region, Part &p, float eps, float t, float phu,
-                                               Local &L, Stages S)
+// Compton kinematics in place: the photon p turns by (t = 1 - cos theta, azimuth uniform
+// phu) and keeps eps E; returns the electron's kinetic energy, with its direction, the one
+// that conserves momentum (incident minus scattered photon momentum), in (eu, ev, ew).
+__device__ __forceinline__ float compton_kin(const Params &P, Part &p, float eps, float t, float phu, float &eu,
+                                             float &ev, float &ew)
 {
     const float E = p.E;
     const float ct = 1.0f - t, st = sqrtf(fmaxf(0.0f, t * (2.0f - t)));
     float sp, cp;
     __sincosf(TWO_PI_F * phu, &sp, &cp);
-    const float Ep = eps * E, T = E - Ep;
-    if (P.diag) ledger(P, p.hist, (double)E - (double)Ep - (double)T);
-    float eu = p.u, ev = p.v, ew = p.w;
-    if (T > 0.0f) {
-        const float pe = sqrtf(T * (T + 2.0f * MEC2F));
-        const float ipe = 1.0f / pe;
-        const float cte = fminf(1.0f, (E - Ep * ct) * ipe), ste = fminf(1.0f, Ep * st * ipe);
-        rotate(eu, ev, ew, cte, ste, -cp, -sp);
-    }
+    const float Ep = eps * E, eT = E - Ep;
+    if (P.diag) ledger(P, p.hist, (double)E - (double)Ep - (double)eT);
+    eu = p.u; ev = p.v; ew = p.w;
     rotate(p.u, p.v, p.w, ct, st, cp, sp);
-    p.E = Ep;
-    emit_electron(P, region, p, T, 1u, eu, ev, ew, L, S);
-    if (Ep < P.pcut) {
-        deposit_point(P, region, p, Ep, L);
-        return false;
+    const float qx = fmaf(-Ep, p.u, E * eu), qy = fmaf(-Ep, p.v, E * ev), qz = fmaf(-Ep, p.w, E * ew);
+    const float q2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+    if (q2 > 0.0f) {
+        const float iq = rsqrtf(q2);
+        eu = qx * iq; ev = qy * iq; ew = qz * iq;
     }
-    return true;
-}
-
-// photoelectric absorption: the electron takes the photon's energy and direction
-__device__ __forceinline__ void photo_absorb(const Params &P, int region, Part &p, Local &L, Stages S)
-{
-    ++L.photo;
-    emit_electron(P, region, p, p.E, 1u, p.u, p.v, p.w, L, S);
+    p.E = Ep;
+    return eT;
 }
 
 // pair production: the electron takes a uniform share u of E - 2 m c^2, the positron the rest,
@@ -369,28 +357,6 @@ __device__ __forceinline__ void pair_produce(const Params &P, int region, Part &
     if (P.diag) ledger(P, p.hist, (double)E - (double)tm - (double)tp);
     emit_electron(P, region, p, tm, 1u, p.u, p.v, p.w, L, S);
     emit_electron(P, region, p, tp, 2u, p.u, p.v, p.w, L, S);
-}
-
-// a complete interaction at p inside material table `tab` (3 rows of NB_PH) at node n,
-// with process uniform rproc
-__device__ __forceinline__ bool photon_interact(const Params &P, int region, Part &p, const float *tab, Node n, float rproc,
-                                                Local &L, Stages S = no_stages())
-{
-    const float fc = lerp_tab(tab + NB_PH, n), fcp = lerp_tab(tab + 2 * NB_PH, n);
-    p.flags &= ~F_UNSCAT;
-    if (rproc < fc) {
-        ++L.compton;
-        float t, phu;
-        const float eps = kn_sample(P, p, p.E, t, phu);
-        return compton_finish(P, region, p, eps, t, phu, L, S);
-    }
-    if (rproc < fcp) {
-        photo_absorb(P, region, p, L, S);
-        return false;
-    }
-    const float4 r = rnd4(p, P);
-    pair_produce(P, region, p, r.x, L, S);
-    return false;
 }
 
 // ---------------------------------------------------------------------------------
@@ -609,22 +575,9 @@ __global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
                 float eT = E, eu = p.u, ev = p.v, ew = p.w;
                 active = false;
                 if (scatter) {
-                    const float ct = 1.0f - t, st = sqrtf(fmaxf(0.0f, t * (2.0f - t)));
-                    float sp, cp;
-                    __sincosf(TWO_PI_F * phu, &sp, &cp);
-                    const float Ep = eps * E;
-                    eT = E - Ep;
-                    if (P.diag) ledger(P, p.hist, (double)E - (double)Ep - (double)eT);
-                    rotate(p.u, p.v, p.w, ct, st, cp, sp);
-                    const float qx = fmaf(-Ep, p.u, E * eu), qy = fmaf(-Ep, p.v, E * ev), qz = fmaf(-Ep, p.w, E * ew);
-                    const float q2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-                    if (q2 > 0.0f) {
-                        const float iq = rsqrtf(q2);
-                        eu = qx * iq; ev = qy * iq; ew = qz * iq;
-                    }
-                    p.E = Ep;
-                    active = Ep >= P.pcut;
-                    if (!active) ledger(P, p.hist, (double)Ep);
+                    eT = compton_kin(P, p, eps, t, phu, eu, ev, ew);
+                    active = p.E >= P.pcut;
+                    if (!active) ledger(P, p.hist, (double)p.E);
                 }
                 Part c;
                 make_child(p, c, 1u);
@@ -665,6 +618,8 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
 
     Win win = win_start();
     bool active = false;
+    bool kn = false;     // a Compton collision whose Klein-Nishina sample is still pending
+    int kn_rounds = 0;
     Part p;
     Local L;
     zero(L);
@@ -677,49 +632,109 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
         if (act == 0) break;
         lane_iters += __popcll(act);
         wave_iters += 64;
-        if (active && !was) ++L.items;
+        if (active && !was) {
+            ++L.items;
+            kn = false;
+        }
         if (!active) continue;
-        const int l = (int)((p.flags & F_LAYER_MASK) >> F_LAYER_SHIFT);
-        const float *tab = lds + l * 3 * NB_PH;
-        const Node nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
-        const float mu = s_rho[l] * lerp_tab(tab, nd);
-        // distance to the slab planes and to the lateral faces
-        float tz = INFINITY;
-        int dl = 0;
-        if (p.w > 0.0f) { tz = (s_zl[l + 1] - p.z) / p.w; dl = 1; }
-        else if (p.w < 0.0f) { tz = (s_zl[l] - p.z) / p.w; dl = -1; }
-        float tl = INFINITY;
-        if (p.u > 0.0f) tl = fminf(tl, (P.hx - p.x) / p.u);
-        else if (p.u < 0.0f) tl = fminf(tl, (-P.hx - p.x) / p.u);
-        if (p.v > 0.0f) tl = fminf(tl, (P.hy - p.y) / p.v);
-        else if (p.v < 0.0f) tl = fminf(tl, (-P.hy - p.y) / p.v);
-        tz = fmaxf(tz, 0.0f);
-        tl = fmaxf(tl, 0.0f);
+        // one Philox draw per lane and iteration (as in the Woodcock kernel): a flight uses it
+        // for the distance, the process and the first Klein-Nishina trial; a pending Compton
+        // sample uses it for two further trials
         const float4 r = rnd4(p, P);
-        const float s = -__logf(r.x) / mu;
-        ++L.steps;
-        if (s < fminf(tz, tl)) {
-            p.x = fmaf(s, p.u, p.x);
-            p.y = fmaf(s, p.v, p.y);
-            p.z = fmaf(s, p.w, p.z);
-            active = photon_interact(P, 1, p, tab, nd, r.y, L, S);
-            continue;
+        bool trial = kn, absorb = false;
+        float u1 = r.x, u2 = r.y;
+        if (!kn) {
+            const int l = (int)((p.flags & F_LAYER_MASK) >> F_LAYER_SHIFT);
+            const float *tab = lds + l * 3 * NB_PH;
+            const Node nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
+            const float mu = s_rho[l] * lerp_tab(tab, nd);
+            // distance to the slab planes and to the lateral faces
+            float tz = INFINITY;
+            int dl = 0;
+            if (p.w > 0.0f) { tz = (s_zl[l + 1] - p.z) / p.w; dl = 1; }
+            else if (p.w < 0.0f) { tz = (s_zl[l] - p.z) / p.w; dl = -1; }
+            float tl = INFINITY;
+            if (p.u > 0.0f) tl = fminf(tl, (P.hx - p.x) / p.u);
+            else if (p.u < 0.0f) tl = fminf(tl, (-P.hx - p.x) / p.u);
+            if (p.v > 0.0f) tl = fminf(tl, (P.hy - p.y) / p.v);
+            else if (p.v < 0.0f) tl = fminf(tl, (-P.hy - p.y) / p.v);
+            tz = fmaxf(tz, 0.0f);
+            tl = fmaxf(tl, 0.0f);
+            const float s = -__logf(r.x) / mu;
+            ++L.steps;
+            if (s < fminf(tz, tl)) {
+                p.x = fmaf(s, p.u, p.x);
+                p.y = fmaf(s, p.v, p.y);
+                p.z = fmaf(s, p.w, p.z);
+                // a collision: r.y picks the process and, rescaled within Compton, is the first
+                // trial's part-and-eps uniform
+                const float fc = lerp_tab(tab + NB_PH, nd);
+                p.flags &= ~F_UNSCAT;
+                if (r.y < fc) {
+                    ++L.compton;
+                    trial = true;
+                    u1 = fminf(r.y / fc, 0.99999994f);
+                    u2 = r.z;
+                } else if (r.y < lerp_tab(tab + 2 * NB_PH, nd)) {
+                    ++L.photo;
+                    absorb = true;
+                } else {
+                    pair_produce(P, 1, p, r.z, L, S);   // rare: kept out of the merged path
+                    active = false;
+                }
+            } else if (tl <= tz) {   // leaves through a lateral face
+                ledger(P, p.hist, (double)p.E);
+                active = false;
+            } else {
+                p.x = fmaf(tz, p.u, p.x);
+                p.y = fmaf(tz, p.v, p.y);
+                const int nlay = l + dl;
+                if (nlay < 0 || nlay >= P.nl) {
+                    ledger(P, p.hist, (double)p.E);
+                    active = false;
+                } else {
+                    p.z = dl > 0 ? s_zl[l + 1] : s_zl[l];
+                    p.flags = (p.flags & ~F_LAYER_MASK) | ((uint32_t)nlay << F_LAYER_SHIFT);
+                }
+            }
         }
-        if (tl <= tz) {   // leaves through a lateral face
-            ledger(P, p.hist, (double)p.E);
+        float eps = 1.0f, t = 0.0f, phu = 0.0f;
+        bool scatter = false;
+        if (trial) {
+            const KN c = kn_setup(p.E);
+#pragma unroll 1
+            for (int k = 0; k < 2; ++k) {
+                scatter = kn_trial(c, u1, u2, eps, t, phu);
+                if (scatter || !kn) break;
+                u1 = r.z;   // a pending sample gets a second trial from the same draw
+                u2 = r.w;
+            }
+            kn_rounds = kn ? kn_rounds + 1 : 0;
+            kn = !scatter;
+            if (kn && kn_rounds > MAX_KN_ROUNDS) {
+                atomicOr(P.err, ERR_SAMPLE);   // unreachable with a sound generator
+                ledger(P, p.hist, (double)p.E);
+                kn = false;
+                active = false;
+            }
+        }
+        if (scatter || absorb) {
+            // one electron set in motion at p, inside the EPID layer the photon is in
+            float eT = p.E, eu = p.u, ev = p.v, ew = p.w;
             active = false;
-            continue;
+            if (scatter) {
+                eT = compton_kin(P, p, eps, t, phu, eu, ev, ew);
+                active = p.E >= P.pcut;
+                if (!active) deposit_point(P, 1, p, p.E, L);
+            }
+            Part c;
+            make_child(p, c, 1u);
+            c.x = p.x; c.y = p.y; c.z = p.z;
+            c.u = eu; c.v = ev; c.w = ew;
+            c.E = eT;
+            if (!P.coupled || eT < P.ecut) deposit_point(P, 1, c, eT, L);
+            else append(P, S, QEE, true, c);
         }
-        p.x = fmaf(tz, p.u, p.x);
-        p.y = fmaf(tz, p.v, p.y);
-        const int nlay = l + dl;
-        if (nlay < 0 || nlay >= P.nl) {
-            ledger(P, p.hist, (double)p.E);
-            active = false;
-            continue;
-        }
-        p.z = dl > 0 ? s_zl[l + 1] : s_zl[l];
-        p.flags = (p.flags & ~F_LAYER_MASK) | ((uint32_t)nlay << F_LAYER_SHIFT);
     }
     stage_flush_all(P, S, 1);
     flush_stats(P, L, S_EPID_PH_STEPS, QGE, lane_iters, wave_iters);
