@@ -73,6 +73,18 @@ WORKLOADS = {
 }
 
 
+def smoothed_sigma_bar(eng, torch, k=15, thr=0.5):
+    """sigma-bar for extrapolation from a noisy image: the pixel set (D >= thr * max D) and
+    each pixel's D are taken from the k x k box mean of the image, each pixel's sigma from
+    its own batch estimate.  Thresholding the raw image at a few tens of percent noise keeps
+    the pixels that fluctuated upwards and understates sigma-bar."""
+    m, v = eng.image()
+    ms = torch.nn.functional.avg_pool2d(m[None, None], k, stride=1, padding=k // 2,
+                                        count_include_pad=False)[0, 0]
+    sel = ms >= thr * ms.max()
+    return float((v[sel].clamp_min(0).sqrt() / ms[sel]).mean())
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +97,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--t1-measured", action="store_true",
+                    help="also run the coupled workload until sigma-bar <= 1% (about 80 s) and time it")
     return ap.parse_args()
 
 
@@ -134,7 +148,10 @@ def main():
     c = eng.counters()
     value = n / dt
     # time to 1%: one delivery's sigma-bar scaled by 1/sqrt(N)
-    t1 = (dt / a.steps if segmented else dt) * (sb / 0.01) ** 2 if sb > 0 else None
+    t_n = dt / a.steps if segmented else dt
+    t1 = t_n * (sb / 0.01) ** 2 if sb > 0 else None
+    sb_s = smoothed_sigma_bar(eng, torch)
+    t1_s = t_n * (sb_s / 0.01) ** 2 if sb_s > 0 else None
 
     # roofline of the dominant kernel: algorithmic lane-ops per launch / average launch time
     units = {1: c["e_steps_phantom"], 0: c["woodcock_steps"], 2: c["epid_photon_steps"], 3: c["e_steps_epid"]}
@@ -184,6 +201,25 @@ def main():
                 "thickness_cm_range": [round(float(th.min()), 3), round(float(th.max()), 3)],
                 "corrected_over_plain": round(float(corrected.sum() / img.sum()), 5)}
 
+    measured = None
+    if a.t1_measured and segmented:
+        print("--t1-measured runs on the coupled workload only (a field's ids end at its total)", file=sys.stderr)
+    elif a.t1_measured:
+        # time to a 1% image measured directly: fresh tally, steps of 2e9 histories (ids
+        # continue past 2^32), sigma-bar checked after each step
+        eng.set_profiling(False)
+        eng.reset()
+        torch.cuda.synchronize()
+        step = 2_000_000_000
+        tm = time.perf_counter()
+        done, sb1 = eng.run_until(0.01, thr=0.5, first=h, step=step, max_hist=1_000_000_000_000)
+        torch.cuda.synchronize()
+        tmd = time.perf_counter() - tm
+        measured = {"s_to_1pct": round(tmd, 2), "histories": done, "sigma_bar": round(sb1, 5),
+                    "sigma_bar_10pct": round(eng.sigma_bar(0.1), 5), "step_histories": step,
+                    "first_history": h}
+        print(json.dumps({"t1pct_measured": measured}), file=sys.stderr, flush=True)
+
     if a.calib_copy:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
@@ -224,12 +260,15 @@ def main():
         "config": {"workload": desc, "name": a.workload,
                    "histories_per_step": n_step, "batches": BATCHES, "tally": "fp64",
                    "first_history": first, "chunk": min(CHUNK, n_step)},
-        "s_to_1pct_extrapolated": round(t1, 2) if t1 else None,
+        "s_to_1pct_extrapolated": round(t1_s, 2) if t1_s else None,
+        "s_to_1pct_extrapolated_raw_selection": round(t1, 2) if t1 else None,
+        "sigma_bar_smoothed_selection": round(sb_s, 5),
         "sigma_bar_at_N": round(sb, 5),
         "N_for_sigma_bar": n_step if segmented else n,
         "roofline": roof,
         "cpu_baseline": cpu,
         "dose_response": response,
+        "t1pct_measured": measured,
         "counters": {k: c[k] for k in ("woodcock_steps", "e_steps_phantom", "e_steps_epid", "epid_photon_steps",
                                        "tally_deposits", "launches", "kernel_ms", "kernel_launches",
                                        "queue_items", "lane_iters", "wave_iters")},

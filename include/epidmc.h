@@ -212,7 +212,9 @@ epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev_ptr, size_t bytes, 
 /* ---- run --------------------------------------------------------------------- */
 /* Transport histories [first_history, first_history + n_histories) on `stream`, split
  * into the configured number of variance batches, and fold them into the tally.
- * Returns after the work has completed.  first + n must not exceed 2^32. */
+ * Returns after the work has completed.  History ids are 64-bit: the random stream of
+ * history h is keyed by the seed and h's high 32 bits, and counted by its low 32 bits, so
+ * ids below 2^32 keep the plain seed key.  A segmented field's ids stay below its total. */
 epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first_history, uint64_t n_histories, void *stream);
 /* Run chunks of `step_histories` from history `first_history` until the mean relative
  * standard deviation over pixels with D >= threshold_frac * max(D) is <= target, or

@@ -795,6 +795,12 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
     Params P = c->P;
     P.h0 = h0;
     P.h1 = h1;
+    // history ids of 2^32 and above: the counter's history word holds the low 32 bits and
+    // the high word selects the key (odd multipliers keep distinct high words distinct);
+    // a chunk never spans a 2^32 boundary, so one key serves the whole chunk
+    const uint32_t hi = (uint32_t)(h0 >> 32);
+    P.key0 ^= hi * 0x9E3779B9u;
+    P.key1 ^= hi * 0x85EBCA6Bu;
     uint32_t *cnt = P.cnt;
     uint32_t *seg = (uint32_t *)(c->ws + c->lay.segc.off);   // [set A, set B, heads][NQ][NSEG] x CSTRIDE
     HIPCHK(launch_zero(cnt, 64, s));
@@ -874,7 +880,7 @@ extern "C" epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first, uint64_t n, v
     if (!c) return EPIDMC_E_ARG;
     REQUIRE(c->bound, EPIDMC_E_NOT_READY, "workspace not bound (call epidmc_bind_workspace after the last set_*)");
     REQUIRE(n >= (uint64_t)c->batches, EPIDMC_E_ARG, "need at least one history per variance batch");
-    REQUIRE(first + n <= (1ull << 32) && first + n > first, EPIDMC_E_RANGE, "history ids must stay below 2^32");
+    REQUIRE(first + n > first, EPIDMC_E_RANGE, "history ids must stay below 2^64");
     if (c->n_seg > 1 && c->n_phsp == 0) {
         uint64_t tot = 0;
         for (uint64_t v : c->seg_hist) tot += v;
@@ -893,6 +899,7 @@ extern "C" epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first, uint64_t n, v
     while (h < first + n) {
         // a chunk ends at the chunk cap, and never spans more than `ring` batches
         uint64_t h1 = std::min(first + n, h + c->lay.chunk);
+        if ((h >> 32) < 0xffffffffull) h1 = std::min(h1, ((h >> 32) + 1) << 32);   // one key per chunk
         const uint64_t b_first = (h - first) * (uint64_t)B / n;
         const uint64_t b_lim = b_first + (uint64_t)ring;   // batches [b_first, b_lim) may be in flight
         if (b_lim < (uint64_t)B) h1 = std::min(h1, batch_start(first, n, B, b_lim));

@@ -255,6 +255,41 @@ def test_sigma_bar_falls_as_inverse_sqrt_n(E):
     assert eng.sigma_bar(0.5) == pytest.approx(sigma_bar(m2, v2, 0.5), rel=1e-9)
 
 
+def test_history_ids_beyond_2_32(E, orc):
+    """History ids are 64-bit: a run across 2^32 equals the runs on either side of it (fixed
+    point: exactly), the block above 2^32 draws different streams from the block below, and
+    histories from id 5e9 pass the same z-gate against the oracle as histories from id 0."""
+    cfg = synth.coupled_hetero_small()
+    b = 1 << 32
+    eng = E.Engine(0, seed=11).configure(cfg, tally=1, batches=2, max_chunk=1 << 16)
+    eng.bind()
+    eng.run(300_000, first=b - 100_000)
+    across = eng.image()[0].cpu().numpy()
+    eng.reset()
+    eng.run(100_000, first=b - 100_000)
+    eng.run(200_000, first=b)
+    split = eng.image()[0].cpu().numpy()
+    assert across.sum() > 0
+    np.testing.assert_array_equal(across, split)
+    eng.reset()
+    eng.run(200_000, first=0)
+    low = eng.image()[0].cpu().numpy()
+    eng.reset()
+    eng.run(200_000, first=b)
+    high = eng.image()[0].cpu().numpy()
+    assert not np.array_equal(low, high)
+
+    cfg = synth.kerma_water()
+    om, ov, *_ = oracle_image(orc, "kerma_water", cfg, 8_000_000)
+    eng = E.Engine(0, seed=1).configure(cfg, batches=64, max_chunk=1 << 24)
+    eng.bind()
+    eng.run(80_000_000, first=5_000_000_000)
+    gm, gv = (t.cpu().numpy() for t in eng.image())
+    g = z_gate(gm, gv, om, ov, thr=0.10, k=4)
+    print("kerma_water z-gate, ids from 5e9", g)
+    assert g["ok"], g
+
+
 def test_run_until_stops_at_target(E):
     cfg = synth.kerma_water(npx=16, pitch=1.6)
     eng = E.Engine(0, seed=4).configure(cfg, batches=64, max_chunk=1 << 22)
