@@ -281,3 +281,45 @@ def response_table_1():
                   [0.995, 0.982, 0.983, 0.996, 0.986],
                   [0.991, 0.997, 1.015, 1.034, 1.043]])
     return t, s, k
+
+
+# --------------------------------------------------------------------------
+# learned denoiser: initial parameters and training fields
+# --------------------------------------------------------------------------
+def unet_params(shapes, seed=21, head_scale=0.01):
+    """Seeded initial parameters for a list of convolution shapes [(name, k, c_in, c_out)]:
+    W[name] of shape (c_out, k, k, c_in) ~ N(0, 2 / (k*k*c_in)) (He), b[name] = 0; the
+    layer named "head" is drawn with standard deviation head_scale instead, so a residual
+    network starts close to its input.  float32, returned as {name: (W, b)}."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for name, k, ci, co in shapes:
+        sd = head_scale if name == "head" else np.sqrt(2.0 / (k * k * ci))
+        W = (rng.standard_normal((co, k, k, ci)) * sd).astype(np.float32)
+        out[name] = (W, np.zeros(co, np.float32))
+    return out
+
+
+def random_aperture(rng, n_pairs=60, leaf_w=0.5, max_gap=10.0, n_hist=1):
+    """One seeded MLC segment: per leaf pair a gap U(0, max_gap) cm around a centre
+    U(-5, 5) cm, pairs outside a random band of rows closed."""
+    g = rng.uniform(0, max_gap, n_pairs)
+    c = rng.uniform(-5, 5, n_pairs)
+    lo, hi = sorted(rng.integers(0, n_pairs, 2))
+    hi = max(hi, lo + 4)
+    g[:lo] = 0.0
+    g[hi:] = 0.0
+    a, b = c - g / 2, c + g / 2
+    return {"n_pairs": n_pairs, "leaf_w": leaf_w, "y0": -0.5 * n_pairs * leaf_w,
+            "a": a[None, :], "b": b[None, :], "counts": np.array([n_hist], np.uint64)}
+
+
+def denoise_field(seed, shape=(128, 128, 64), spacing=0.4, npx=(768, 1024), pitch=0.039):
+    """A training or evaluation field for the denoiser: the coupled workload's source and
+    EPID with a seeded ellipsoid phantom (4 mm voxels by default) and one seeded MLC
+    segment.  Returns a workload configuration."""
+    rng = np.random.default_rng(10_000 + seed)
+    cfg = coupled_hetero(shape=shape, spacing=spacing, npx=npx, pitch=pitch, phantom_seed=20_000 + seed)
+    cfg["name"] = f"denoise_field_{seed}"
+    cfg["source"]["aperture"] = random_aperture(rng)
+    return cfg
