@@ -112,9 +112,11 @@ def upsample_backward(g):
 # ---------------------------------------------------------------------------------------
 def normalise(noisy, thickness):
     """Network input and scale from a batch of images (N, H, W) and thickness maps:
-    s = mean of each noisy image over its frame; x = [noisy / s, thickness / 20 cm]."""
+    s = mean of each noisy image over its frame (1 when that mean is not positive, e.g. an
+    empty image); x = [noisy / s, thickness / 20 cm]."""
     noisy = np.asarray(noisy, np.float64)
     s = noisy.reshape(noisy.shape[0], -1).mean(axis=1)
+    s = np.where(s > 0, s, 1.0)
     x = np.stack([noisy / s[:, None, None], np.asarray(thickness, np.float64) / THICK_SCALE], axis=-1)
     return x, s
 

@@ -71,6 +71,8 @@ class Counters(ct.Structure):
         return d
 
 
+from .denoise import DN_EXPORTS, declare as declare_denoiser  # noqa: E402
+
 EXPORTS = [
     "epidmc_create", "epidmc_destroy", "epidmc_last_error", "epidmc_set_materials", "epidmc_set_physics",
     "epidmc_set_phantom_hu", "epidmc_set_phantom_direct", "epidmc_set_epid", "epidmc_set_source_spectrum",
@@ -80,7 +82,7 @@ EXPORTS = [
     "epidmc_sigma_bar", "epidmc_reset_tally", "epidmc_get_counters",
     "epidmc_radiological_thickness", "epidmc_field_size", "epidmc_dose_response",
     "epidmc_debug_philox", "epidmc_debug_sample", "epidmc_debug_table",
-]
+] + DN_EXPORTS
 
 _lib = None
 
@@ -129,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         f.restype = ct.c_int
     L.epidmc_last_error.argtypes = [vp]
     L.epidmc_last_error.restype = ct.c_char_p
+    declare_denoiser(L)
     _lib = L
     return L
 

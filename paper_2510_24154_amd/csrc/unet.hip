@@ -1,0 +1,1166 @@
+// Learned denoiser of low-count EPID images (Sec. 4.1): a 4-level U-Net in BF16 with FP32
+// accumulation on the gfx950 matrix cores, its training (backward passes and Adam), and the
+// C ABI of epidmc_denoise.h.
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16.  The reduction index runs
+// over groups of 8 input channels of one tap ("k-groups", kg = tap * c_in/8 + channel
+// group), so every MFMA operand is one 16-byte load of 8 consecutive NHWC channels:
+//   forward / backward-data   rows = pixels, columns = output channels; each lane loads its
+//                             A row (one pixel's 8 channels at the shifted position) and
+//                             B column (8 weights) straight from memory -- the 3x3 halo
+//                             re-reads hit L1/L2;
+//   backward-weights          rows = output channels, columns = (tap, input channel), the
+//                             reduction runs over pixels, so both operands are staged
+//                             through LDS transposed; pixel chunks give FP32 partials that
+//                             a second kernel adds in a fixed order (deterministic).
+// The backward-data convolution is the forward kernel on the gradient with the weights'
+// channels transposed and taps reversed, its ReLU derivative fused as an output gate.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "epidmc_denoise.h"
+
+namespace dn {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WG = 256;
+
+__device__ __forceinline__ uint16_t f2bf(float f)   // round to nearest even (finite inputs)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ float lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+__device__ __forceinline__ uint32_t pack(float a, float b) { return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16); }
+
+__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// convolution (forward and backward-data)
+// ---------------------------------------------------------------------------------------
+struct ConvArgs {
+    const uint16_t *x, *w, *gate;
+    const float *bias;
+    uint16_t *y;
+    long long P;             // pixels n * h * w
+    int ldx, ldy, ldg, cin, cout, h, wd, relu;
+    int cg_shift, kg_total;  // log2(c_in / 8), k * k * c_in / 8
+};
+
+// A wave computes 64 pixels (4 row tiles) x NT*16 output channels; the 4 waves of a block
+// take consecutive pixel tiles and share the weight columns.
+template <int KS, int NT>
+__global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    const long long p0 = ((long long)blockIdx.x * 4 + wave) * 64;
+    const int co0 = blockIdx.y * NT * 16;
+    const int hw = a.h * a.wd;
+    int py[4], px[4];
+    long long pbase[4];
+    bool pv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const long long p = p0 + m * 16 + row;
+        pv[m] = p < a.P;
+        const long long pc = pv[m] ? p : 0;
+        const int n = (int)(pc / hw), r = (int)(pc - (long long)n * hw);
+        py[m] = r / a.wd;
+        px[m] = r - py[m] * a.wd;
+        pbase[m] = (long long)n * hw;
+    }
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int kstride = a.kg_total * 8;
+    const uint16_t *wrow[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) wrow[t] = a.w + (long long)(co0 + t * 16 + row) * kstride;
+    const int steps = (a.kg_total + 3) >> 2;
+    const int cmask = (1 << a.cg_shift) - 1;
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (int s = 0; s < steps; ++s) {
+        const int kg = s * 4 + grp;
+        const bool kv = kg < a.kg_total;
+        const int tap = kg >> a.cg_shift, cg = kg & cmask;
+        const int dy = KS == 3 ? tap / 3 - 1 : 0;
+        const int dx = KS == 3 ? tap - (tap / 3) * 3 - 1 : 0;
+        u32x4 A[4], B[NT];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int yy = py[m] + dy, xx = px[m] + dx;
+            const bool ok = kv && pv[m] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.wd;
+            const long long off = ok ? ((pbase[m] + (long long)yy * a.wd + xx) * a.ldx + cg * 8) : 0;
+            const u32x4 v = *(const u32x4 *)(a.x + off);
+            A[m] = ok ? v : zero;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const u32x4 v = *(const u32x4 *)(wrow[t] + (kv ? kg * 8 : 0));
+            B[t] = kv ? v : zero;
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+    }
+    // lane holds rows 4*grp + r of each 16-pixel tile, column `row` of each channel tile
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = co0 + t * 16 + row;
+        const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long p = p0 + m * 16 + grp * 4 + r;
+                if (p >= a.P) continue;
+                float v = acc[m][t][r] + b;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.gate && !(bf2f(a.gate[p * a.ldg + co]) > 0.0f)) v = 0.0f;
+                a.y[p * a.ldy + co] = f2bf(v);
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// backward-weights convolution
+// ---------------------------------------------------------------------------------------
+struct WgArgs {
+    const uint16_t *x, *g;
+    float *part, *dbpart;
+    long long P;
+    int ldx, ldg, cin, cout, h, wd, cg_shift, kg_total, cols, cols_pad, chunk_px;
+};
+
+// Block tile: TM = 32 * WM output channels x TN = 32 * (4 / WM) columns; each wave a 32 x 32
+// sub-tile (2 x 2 MFMA tiles).  Per 32-pixel step the block stages g (pixels x channels)
+// and the shifted input (pixels x columns) into LDS transposed, so that a lane's operand is
+// 8 consecutive pixels of one row.
+template <int KS, int WM>
+__global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
+{
+    constexpr int TM = 32 * WM, TN = 32 * (4 / WM), PITCH = 40;   // 80-byte rows
+    __shared__ __align__(16) uint16_t Gt[TM * PITCH];
+    __shared__ __align__(16) uint16_t Xt[TN * PITCH];
+    __shared__ float red[WG][9];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int co0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
+    const long long pc0 = (long long)blockIdx.z * a.chunk_px;
+    const long long pc1 = min(pc0 + (long long)a.chunk_px, a.P);
+    const int hw = a.h * a.wd;
+    const int cmask = (1 << a.cg_shift) - 1;
+    const bool do_db = a.dbpart && blockIdx.y == 0;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbacc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dbacc[j] = 0.0f;
+    constexpr int GI = 32 * TM / 8, XI = 32 * TN / 8;   // 16-byte items per tile
+    for (long long pb = pc0; pb < pc1; pb += 32) {
+        if (tid < GI) {
+            const int pp = tid / (TM / 8), c8 = tid % (TM / 8);
+            const long long p = pb + pp;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (p < pc1) v = *(const u32x4 *)(a.g + p * a.ldg + co0 + c8 * 8);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                Gt[(c8 * 8 + 2 * j) * PITCH + pp] = (uint16_t)(v[j] & 0xFFFFu);
+                Gt[(c8 * 8 + 2 * j + 1) * PITCH + pp] = (uint16_t)(v[j] >> 16);
+                dbacc[2 * j] += lo(v[j]);
+                dbacc[2 * j + 1] += hi(v[j]);
+            }
+        }
+        for (int it = tid; it < XI; it += WG) {
+            const int pp = it / (TN / 8), kl = it % (TN / 8);
+            const int kg = col0 / 8 + kl;
+            const long long p = pb + pp;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (p < pc1 && kg < a.kg_total) {
+                const int tap = kg >> a.cg_shift, cg = kg & cmask;
+                const int n = (int)(p / hw), r = (int)(p - (long long)n * hw);
+                const int y = r / a.wd + (KS == 3 ? tap / 3 - 1 : 0);
+                const int x = r % a.wd + (KS == 3 ? tap % 3 - 1 : 0);
+                if (y >= 0 && y < a.h && x >= 0 && x < a.wd)
+                    v = *(const u32x4 *)(a.x + ((long long)n * hw + (long long)y * a.wd + x) * a.ldx + cg * 8);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                Xt[(kl * 8 + 2 * j) * PITCH + pp] = (uint16_t)(v[j] & 0xFFFFu);
+                Xt[(kl * 8 + 2 * j + 1) * PITCH + pp] = (uint16_t)(v[j] >> 16);
+            }
+        }
+        __syncthreads();
+        u32x4 A[2], B[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            A[i] = *(const u32x4 *)(Gt + (wm * 32 + i * 16 + (lane & 15)) * PITCH + 8 * (lane >> 4));
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            B[j] = *(const u32x4 *)(Xt + (wn * 32 + j * 16 + (lane & 15)) * PITCH + 8 * (lane >> 4));
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma(A[i], B[j], acc[i][j]);
+        __syncthreads();
+    }
+    float *dst = a.part + (size_t)blockIdx.z * a.cout * a.cols_pad;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = co0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int col = col0 + wn * 32 + j * 16 + (lane & 15);
+                dst[(size_t)co * a.cols_pad + col] = acc[i][j][r];
+            }
+    if (do_db) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[tid][j] = dbacc[j];
+        __syncthreads();
+        if (tid < TM) {   // channel co0 + tid = group c8 = tid / 8, element tid % 8
+            float s = 0.0f;
+            for (int pp = 0; pp < 32; ++pp) s += red[pp * (TM / 8) + tid / 8][tid % 8];
+            a.dbpart[(size_t)blockIdx.z * a.cout + co0 + tid] = s;
+        }
+    }
+}
+
+__global__ void k_wgrad_reduce(const float *part, const float *dbpart, int nchunk, int cout, int cols, int cols_pad,
+                               float *dw, float *db)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nw = (long long)cout * cols;
+    if (i < nw) {
+        const int co = (int)(i / cols), col = (int)(i - (long long)co * cols);
+        float s = 0.0f;
+        for (int c = 0; c < nchunk; ++c) s += part[((size_t)c * cout + co) * cols_pad + col];
+        dw[i] = s;
+    } else if (db && i < nw + cout) {
+        const int co = (int)(i - nw);
+        float s = 0.0f;
+        for (int c = 0; c < nchunk; ++c) s += dbpart[(size_t)c * cout + co];
+        db[co] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// weights, pooling, upsampling, skip gradient
+// ---------------------------------------------------------------------------------------
+__global__ void k_weights(const float *w, int cout, int kk, int cin, uint16_t *wf, uint16_t *wb)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)cout * kk * cin) return;
+    const int c = (int)(i % cin), tap = (int)((i / cin) % kk), o = (int)(i / ((long long)cin * kk));
+    const uint16_t v = f2bf(w[i]);
+    if (wf) wf[i] = v;
+    if (wb) wb[((long long)c * kk + (kk - 1 - tap)) * cout + o] = v;
+}
+
+// one thread per (output pixel, 8-channel group)
+__global__ void k_pool(const uint16_t *x, int ldx, uint16_t *y, int ldy, int c, int n, int h, int wd)
+{
+    const int G = c / 8, ho = h / 2, wo = wd / 2;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * ho * wo * G) return;
+    const int g = (int)(i % G);
+    const long long q = i / G;
+    const int xo = (int)(q % wo), yo = (int)((q / wo) % ho), im = (int)(q / ((long long)wo * ho));
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const long long p = ((long long)im * h + 2 * yo + a) * wd + 2 * xo + b;
+            const u32x4 v = *(const u32x4 *)(x + p * ldx + g * 8);
+            for (int j = 0; j < 4; ++j) { s[2 * j] += lo(v[j]); s[2 * j + 1] += hi(v[j]); }
+        }
+    u32x4 o;
+    for (int j = 0; j < 4; ++j) o[j] = pack(0.25f * s[2 * j], 0.25f * s[2 * j + 1]);
+    *(u32x4 *)(y + q * ldy + g * 8) = o;
+}
+
+// one thread per (input pixel, group), writing its 2 x 2 block
+__global__ void k_upsample(const uint16_t *x, int ldx, uint16_t *y, int ldy, int c, int n, int h, int wd)
+{
+    const int G = c / 8;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * h * wd * G) return;
+    const int g = (int)(i % G);
+    const long long q = i / G;
+    const int xi = (int)(q % wd), yi = (int)((q / wd) % h), im = (int)(q / ((long long)wd * h));
+    const u32x4 v = *(const u32x4 *)(x + q * ldx + g * 8);
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const long long p = ((long long)im * 2 * h + 2 * yi + a) * (2 * wd) + 2 * xi + b;
+            *(u32x4 *)(y + p * ldy + g * 8) = v;
+        }
+}
+
+__global__ void k_upsample_bwd(const uint16_t *gi, int ldg, uint16_t *y, int ldy, int c, int n, int h, int wd)
+{
+    const int G = c / 8, ho = h / 2, wo = wd / 2;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * ho * wo * G) return;
+    const int g = (int)(i % G);
+    const long long q = i / G;
+    const int xo = (int)(q % wo), yo = (int)((q / wo) % ho), im = (int)(q / ((long long)wo * ho));
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const long long p = ((long long)im * h + 2 * yo + a) * wd + 2 * xo + b;
+            const u32x4 v = *(const u32x4 *)(gi + p * ldg + g * 8);
+            for (int j = 0; j < 4; ++j) { s[2 * j] += lo(v[j]); s[2 * j + 1] += hi(v[j]); }
+        }
+    u32x4 o;
+    for (int j = 0; j < 4; ++j) o[j] = pack(s[2 * j], s[2 * j + 1]);
+    *(u32x4 *)(y + q * ldy + g * 8) = o;
+}
+
+__global__ void k_skip_bwd(const uint16_t *gs, int lds, const uint16_t *gp, int ldp, const uint16_t *act, int lda,
+                           uint16_t *out, int ldo, int c, int n, int h, int wd)
+{
+    const int G = c / 8;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)n * h * wd * G) return;
+    const int g = (int)(i % G);
+    const long long q = i / G;
+    const int x = (int)(q % wd), y = (int)((q / wd) % h), im = (int)(q / ((long long)wd * h));
+    const long long qp = ((long long)im * (h / 2) + y / 2) * (wd / 2) + x / 2;
+    const u32x4 a = *(const u32x4 *)(gs + q * lds + g * 8);
+    const u32x4 b = *(const u32x4 *)(gp + qp * ldp + g * 8);
+    const u32x4 m = *(const u32x4 *)(act + q * lda + g * 8);
+    u32x4 o;
+    for (int j = 0; j < 4; ++j) {
+        const float v0 = lo(m[j]) > 0.0f ? lo(a[j]) + 0.25f * lo(b[j]) : 0.0f;
+        const float v1 = hi(m[j]) > 0.0f ? hi(a[j]) + 0.25f * hi(b[j]) : 0.0f;
+        o[j] = pack(v0, v1);
+    }
+    *(u32x4 *)(out + q * ldo + g * 8) = o;
+}
+
+// ---------------------------------------------------------------------------------------
+// input normalisation, head and loss, Adam
+// ---------------------------------------------------------------------------------------
+// partial sums of each image: grid (blocks per image, images)
+__global__ void k_img_sum(const double *img, long long hw, int nb, double *part)
+{
+    __shared__ double sh[WG];
+    const int im = blockIdx.y;
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * WG + threadIdx.x; i < hw; i += (long long)nb * WG)
+        s += img[(long long)im * hw + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = WG / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[im * nb + blockIdx.x] = sh[0];
+}
+
+// scale of image i: its mean (1 for an image whose mean is not positive)
+__global__ void k_img_scale(const double *part, int nb, long long hw, int n, double *s)
+{
+    const int im = blockIdx.x * blockDim.x + threadIdx.x;
+    if (im >= n) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += part[im * nb + b];
+    const double m = t / (double)hw;
+    s[im] = m > 0.0 ? m : 1.0;
+}
+
+__global__ void k_prepare(const double *noisy, const double *thick, const double *target, const double *s,
+                          long long hw, long long P, uint16_t *x, float *x0, float *tgt)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double inv = 1.0 / s[p / hw];
+    const double v = noisy[p] * inv;
+    u32x4 o = {pack((float)v, (float)(thick[p] * (1.0 / 20.0))), 0u, 0u, 0u};
+    *(u32x4 *)(x + p * 8) = o;
+    x0[p] = (float)v;
+    if (target) tgt[p] = (float)(target[p] * inv);
+}
+
+// per pixel: r = bh + wh . t0[p]; out = x0 + r.  Training (tgt != NULL): squared error,
+// dL/dr = 2 (out - tgt) / P, gradient at t0 gated by t0 > 0, and per-block partial sums of
+// the loss, dL/db and dL/dw (34 floats per block).  Inference: out * s to `img`.
+constexpr int HC = 32;   // head input channels
+__global__ __launch_bounds__(WG) void k_head(const uint16_t *t0, const float *wh, const float *bh, const float *x0,
+                                             const float *tgt,
+                                             const double *s, long long hw, long long P, double *img, uint16_t *g0,
+                                             float *part)
+{
+    __shared__ float red[WG / 64][HC + 2];
+    const long long p = (long long)blockIdx.x * WG + threadIdx.x;
+    const bool live = p < P;
+    float t[HC];
+    const u32x4 *src = (const u32x4 *)(t0 + (live ? p : 0) * HC);
+#pragma unroll
+    for (int q = 0; q < HC / 8; ++q) {
+        const u32x4 v = src[q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { t[8 * q + 2 * j] = lo(v[j]); t[8 * q + 2 * j + 1] = hi(v[j]); }
+    }
+    float r = bh[0];
+#pragma unroll
+    for (int c = 0; c < HC; ++c) r += wh[c] * t[c];
+    const float out = (live ? x0[p] : 0.0f) + r;
+    if (!tgt) {
+        if (live) img[p] = (double)out * s[p / hw];
+        return;
+    }
+    const float d = live ? out - tgt[p] : 0.0f;
+    const float gr = 2.0f * d / (float)P;
+    if (live) {
+        u32x4 *dst = (u32x4 *)(g0 + p * HC);
+#pragma unroll
+        for (int q = 0; q < HC / 8; ++q) {
+            u32x4 o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 8 * q + 2 * j;
+                o[j] = pack(t[c] > 0.0f ? gr * wh[c] : 0.0f, t[c + 1] > 0.0f ? gr * wh[c + 1] : 0.0f);
+            }
+            dst[q] = o;
+        }
+    }
+    float v[HC + 2];
+#pragma unroll
+    for (int c = 0; c < HC; ++c) v[c] = gr * t[c];
+    v[HC] = gr;
+    v[HC + 1] = d * d;
+#pragma unroll
+    for (int c = 0; c < HC + 2; ++c)
+        for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int c = 0; c < HC + 2; ++c) red[wave][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x < HC + 2) {
+        float sum = 0.0f;
+        for (int w = 0; w < WG / 64; ++w) sum += red[w][threadIdx.x];
+        part[(size_t)blockIdx.x * (HC + 2) + threadIdx.x] = sum;
+    }
+}
+
+// dw (HC floats), db, and loss = sum of squares / P, from the blocks' partials
+__global__ void k_head_reduce(const float *part, int nblk, long long P, float *dw, float *db, double *loss)
+{
+    const int c = threadIdx.x;
+    if (c >= HC + 2) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (HC + 2) + c];
+    if (c < HC) dw[c] = (float)s;
+    else if (c == HC) db[0] = (float)s;
+    else if (loss) loss[0] = s / (double)P;
+}
+
+__global__ void k_adam(float *th, const float *g, float *m, float *v, long long n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    th[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+__global__ void k_fill_f32(float *p, long long n, float v)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_copy_f32(const float *a, float *b, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------
+static inline unsigned nblocks(long long n, int per = WG) { return (unsigned)((n + per - 1) / per); }
+static int ilog2(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_t *w, const float *bias, uint16_t *y,
+                              int ldy, int cout, const uint16_t *gate, int ldg, int n, int h, int wd, int k, int relu,
+                              hipStream_t s)
+{
+    ConvArgs a;
+    a.x = x; a.w = w; a.gate = gate; a.bias = bias; a.y = y;
+    a.P = (long long)n * h * wd;
+    a.ldx = ldx; a.ldy = ldy; a.ldg = ldg; a.cin = cin; a.cout = cout; a.h = h; a.wd = wd; a.relu = relu;
+    a.cg_shift = ilog2(cin / 8);
+    a.kg_total = k * k * cin / 8;
+    if (a.P == 0) return hipSuccess;
+    const bool wide = cout % 64 == 0;
+    dim3 grid(nblocks(a.P, 256), cout / (wide ? 64 : 32));
+    if (k == 3) {
+        if (wide) hipLaunchKernelGGL((k_conv<3, 4>), grid, dim3(WG), 0, s, a);
+        else hipLaunchKernelGGL((k_conv<3, 2>), grid, dim3(WG), 0, s, a);
+    } else {
+        if (wide) hipLaunchKernelGGL((k_conv<1, 4>), grid, dim3(WG), 0, s, a);
+        else hipLaunchKernelGGL((k_conv<1, 2>), grid, dim3(WG), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+struct WgPlan {
+    int wm, tm, tn, cols, cols_pad, chunk_px, nchunk;
+    size_t floats;   // partials of dw and db
+};
+
+static WgPlan wgrad_plan(long long P, int k, int cin, int cout)
+{
+    WgPlan q;
+    q.wm = cout % 64 == 0 ? 2 : 1;
+    q.tm = 32 * q.wm;
+    q.tn = 32 * (4 / q.wm);
+    q.cols = k * k * cin;
+    q.cols_pad = (q.cols + q.tn - 1) / q.tn * q.tn;
+    const long long tiles = (long long)(cout / q.tm) * (q.cols_pad / q.tn);
+    long long c = (P * tiles + 2047) / 2048;           // about 2048 blocks in all
+    c = std::max<long long>(256, (c + 31) / 32 * 32);
+    q.chunk_px = (int)std::min<long long>(c, 1 << 20);
+    q.nchunk = (int)std::max<long long>(1, (P + q.chunk_px - 1) / q.chunk_px);
+    q.floats = (size_t)q.nchunk * cout * q.cols_pad + (size_t)q.nchunk * cout;
+    return q;
+}
+
+static hipError_t launch_wgrad(const uint16_t *x, int ldx, int cin, const uint16_t *g, int ldg, int cout, int n, int h,
+                               int wd, int k, float *dw, float *db, float *scratch, hipStream_t s)
+{
+    const long long P = (long long)n * h * wd;
+    const WgPlan q = wgrad_plan(P, k, cin, cout);
+    WgArgs a;
+    a.x = x; a.g = g; a.part = scratch; a.dbpart = db ? scratch + (size_t)q.nchunk * cout * q.cols_pad : nullptr;
+    a.P = P; a.ldx = ldx; a.ldg = ldg; a.cin = cin; a.cout = cout; a.h = h; a.wd = wd;
+    a.cg_shift = ilog2(cin / 8); a.kg_total = k * k * cin / 8;
+    a.cols = q.cols; a.cols_pad = q.cols_pad; a.chunk_px = q.chunk_px;
+    dim3 grid(cout / q.tm, q.cols_pad / q.tn, q.nchunk);
+    if (k == 3) {
+        if (q.wm == 2) hipLaunchKernelGGL((k_wgrad<3, 2>), grid, dim3(WG), 0, s, a);
+        else hipLaunchKernelGGL((k_wgrad<3, 1>), grid, dim3(WG), 0, s, a);
+    } else {
+        if (q.wm == 2) hipLaunchKernelGGL((k_wgrad<1, 2>), grid, dim3(WG), 0, s, a);
+        else hipLaunchKernelGGL((k_wgrad<1, 1>), grid, dim3(WG), 0, s, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long tot = (long long)cout * q.cols + (db ? cout : 0);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(tot)), dim3(WG), 0, s, (const float *)a.part,
+                       (const float *)a.dbpart, q.nchunk, cout, q.cols, q.cols_pad, dw, db);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// the network runner
+// ---------------------------------------------------------------------------------------
+constexpr int LEVELS = 4, BASE = 32, NL = 18;
+
+struct Layer {
+    char name[8];
+    int k, cin, cout;
+    size_t ow, ob;   // offsets in the flat parameter vector (floats)
+};
+
+struct Buf {
+    size_t off = 0, bytes = 0;
+};
+
+}  // namespace dn
+
+using namespace dn;
+
+struct epidmc_unet {
+    int device = 0;
+    std::string err;
+    Layer L[NL];
+    size_t nparam = 0;
+    // bound shape and workspace
+    bool bound = false;
+    int n = 0, h = 0, w = 0;
+    char *ws = nullptr;
+    bool have_params = false;
+    int t = 0;   // Adam steps taken
+    struct {
+        Buf X, x0, tgt, scale, sumpart, headpart, wgs;
+        Buf theta, m, v, grad, wf, wb;
+        Buf ea[LEVELS], cat[LEVELS - 1], eb3, pl[LEVELS - 1], ul[LEVELS - 1], da[LEVELS - 1], db[LEVELS - 1];
+        Buf gdb[LEVELS - 1], gda[LEVELS - 1], gcat[LEVELS - 1], gul[LEVELS - 1], geb[LEVELS], gea[LEVELS],
+            gp[LEVELS - 1];
+        size_t total = 0;
+    } lay;
+    int sum_nb = 0;
+    long long head_blocks = 0;
+};
+
+namespace dn {
+
+static epidmc_status fail(const epidmc_unet *u, epidmc_status code, const std::string &msg)
+{
+    if (u) const_cast<epidmc_unet *>(u)->err = msg;
+    return code;
+}
+
+#define UREQ(cond, code, msg) \
+    do { if (!(cond)) return fail(u, code, msg); } while (0)
+#define UCHK(x)                                                                                         \
+    do {                                                                                                \
+        hipError_t e_ = (x);                                                                            \
+        if (e_ != hipSuccess) return fail(u, EPIDMC_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static int chan(int l) { return BASE << l; }
+
+static void make_layers(epidmc_unet *u)
+{
+    int i = 0;
+    auto add = [&](const char *nm, int k, int ci, int co) {
+        Layer &x = u->L[i++];
+        std::snprintf(x.name, sizeof x.name, "%s", nm);
+        x.k = k; x.cin = ci; x.cout = co;
+    };
+    char nm[8];
+    int prev = 8;
+    for (int l = 0; l < LEVELS; ++l) {
+        std::snprintf(nm, 8, "e%da", l); add(nm, 3, prev, chan(l));
+        std::snprintf(nm, 8, "e%db", l); add(nm, 3, chan(l), chan(l));
+        prev = chan(l);
+    }
+    for (int l = LEVELS - 2; l >= 0; --l) {
+        std::snprintf(nm, 8, "u%d", l); add(nm, 1, chan(l + 1), chan(l));
+        std::snprintf(nm, 8, "d%da", l); add(nm, 3, 2 * chan(l), chan(l));
+        std::snprintf(nm, 8, "d%db", l); add(nm, 3, chan(l), chan(l));
+    }
+    add("head", 1, chan(0), 1);
+    size_t off = 0;
+    for (int j = 0; j < NL; ++j) {   // 64-float alignment keeps every BF16 row 16-byte aligned
+        Layer &x = u->L[j];
+        x.ow = off;
+        off += ((size_t)x.cout * x.k * x.k * x.cin + 63) / 64 * 64;
+        x.ob = off;
+        off += ((size_t)x.cout + 63) / 64 * 64;
+    }
+    u->nparam = off;
+}
+
+static int find(const epidmc_unet *u, const char *nm)
+{
+    for (int j = 0; j < NL; ++j)
+        if (!std::strcmp(u->L[j].name, nm)) return j;
+    return -1;
+}
+
+static size_t plan(epidmc_unet *u, int n, int h, int w)
+{
+    auto &y = u->lay;
+    size_t off = 0;
+    auto take = [&](Buf &b, size_t bytes) { b.off = off; b.bytes = bytes; off += (bytes + 255) / 256 * 256; };
+    auto P = [&](int l) { return (size_t)n * (size_t)(h >> l) * (size_t)(w >> l); };
+    take(y.X, P(0) * 8 * 2);
+    take(y.x0, P(0) * 4);
+    take(y.tgt, P(0) * 4);
+    take(y.scale, (size_t)n * 8);
+    u->sum_nb = 64;
+    take(y.sumpart, (size_t)n * u->sum_nb * 8);
+    u->head_blocks = (long long)((P(0) + WG - 1) / WG);
+    take(y.headpart, (size_t)u->head_blocks * (HC + 2) * 4);
+    size_t wg = 0;
+    for (int j = 0; j < NL - 1; ++j) {
+        const Layer &x = u->L[j];
+        int lev = 0;
+        if (x.name[0] == 'e' || x.name[0] == 'd') lev = x.name[1] - '0';
+        else lev = x.name[1] - '0' + 1;   // u{l} runs at level l+1
+        wg = std::max(wg, wgrad_plan((long long)P(lev), x.k, x.cin, x.cout).floats);
+    }
+    take(y.wgs, wg * 4);
+    const size_t np = u->nparam;
+    take(y.theta, np * 4); take(y.m, np * 4); take(y.v, np * 4); take(y.grad, np * 4);
+    take(y.wf, np * 2); take(y.wb, np * 2);
+    for (int l = 0; l < LEVELS; ++l) {
+        take(y.ea[l], P(l) * chan(l) * 2);
+        take(y.gea[l], P(l) * chan(l) * 2);
+        take(y.geb[l], P(l) * chan(l) * 2);
+    }
+    take(y.eb3, P(LEVELS - 1) * chan(LEVELS - 1) * 2);
+    for (int l = 0; l < LEVELS - 1; ++l) {
+        take(y.cat[l], P(l) * 2 * chan(l) * 2);
+        take(y.gcat[l], P(l) * 2 * chan(l) * 2);
+        take(y.pl[l], P(l + 1) * chan(l) * 2);
+        take(y.gp[l], P(l + 1) * chan(l) * 2);
+        take(y.ul[l], P(l + 1) * chan(l) * 2);
+        take(y.gul[l], P(l + 1) * chan(l) * 2);
+        take(y.da[l], P(l) * chan(l) * 2);
+        take(y.gda[l], P(l) * chan(l) * 2);
+        take(y.db[l], P(l) * chan(l) * 2);
+        take(y.gdb[l], P(l) * chan(l) * 2);
+    }
+    y.total = off;
+    return off;
+}
+
+template <class T> static T *at(epidmc_unet *u, const Buf &b) { return (T *)(u->ws + b.off); }
+
+static hipError_t weights_all(epidmc_unet *u, hipStream_t s)
+{
+    for (int j = 0; j < NL - 1; ++j) {
+        const Layer &x = u->L[j];
+        const long long cnt = (long long)x.cout * x.k * x.k * x.cin;
+        hipLaunchKernelGGL(k_weights, dim3(nblocks(cnt)), dim3(WG), 0, s, at<float>(u, u->lay.theta) + x.ow, x.cout,
+                           x.k * x.k, x.cin, at<uint16_t>(u, u->lay.wf) + x.ow, at<uint16_t>(u, u->lay.wb) + x.ow);
+    }
+    return hipGetLastError();
+}
+
+// normalise the batch: scale, 8-channel BF16 input, FP32 image channel and target
+static hipError_t prepare(epidmc_unet *u, const double *noisy, const double *thick, const double *target, int n,
+                          hipStream_t s)
+{
+    auto &y = u->lay;
+    const long long hw = (long long)u->h * u->w, P = hw * n;
+    hipLaunchKernelGGL(k_img_sum, dim3(u->sum_nb, n), dim3(WG), 0, s, noisy, hw, u->sum_nb, at<double>(u, y.sumpart));
+    hipLaunchKernelGGL(k_img_scale, dim3(nblocks(n, 64)), dim3(64), 0, s, (const double *)at<double>(u, y.sumpart),
+                       u->sum_nb, hw, n, at<double>(u, y.scale));
+    hipLaunchKernelGGL(k_prepare, dim3(nblocks(P)), dim3(WG), 0, s, noisy, thick, target,
+                       (const double *)at<double>(u, y.scale), hw, P, at<uint16_t>(u, y.X), at<float>(u, y.x0),
+                       at<float>(u, y.tgt));
+    return hipGetLastError();
+}
+
+static hipError_t forward(epidmc_unet *u, int n, hipStream_t s)
+{
+    auto &y = u->lay;
+    const uint16_t *wf = at<uint16_t>(u, y.wf);
+    const float *th = at<float>(u, y.theta);
+    hipError_t e;
+    for (int l = 0; l < LEVELS; ++l) {
+        const int c = chan(l), hl = u->h >> l, wl = u->w >> l;
+        const Layer &A = u->L[2 * l], &B = u->L[2 * l + 1];
+        const uint16_t *in = l == 0 ? at<uint16_t>(u, y.X) : at<uint16_t>(u, y.pl[l - 1]);
+        const int ldin = l == 0 ? 8 : chan(l - 1);
+        if ((e = launch_conv(in, ldin, A.cin, wf + A.ow, th + A.ob, at<uint16_t>(u, y.ea[l]), c, c, nullptr, 0, n, hl,
+                             wl, 3, 1, s)) != hipSuccess) return e;
+        uint16_t *out = l < LEVELS - 1 ? at<uint16_t>(u, y.cat[l]) : at<uint16_t>(u, y.eb3);
+        const int ldo = l < LEVELS - 1 ? 2 * c : c;
+        if ((e = launch_conv(at<uint16_t>(u, y.ea[l]), c, c, wf + B.ow, th + B.ob, out, ldo, c, nullptr, 0, n, hl, wl,
+                             3, 1, s)) != hipSuccess) return e;
+        if (l < LEVELS - 1) {
+            const long long items = (long long)n * (hl / 2) * (wl / 2) * (c / 8);
+            hipLaunchKernelGGL(k_pool, dim3(nblocks(items)), dim3(WG), 0, s, (const uint16_t *)out, ldo,
+                               at<uint16_t>(u, y.pl[l]), c, c, n, hl, wl);
+        }
+    }
+    for (int l = LEVELS - 2; l >= 0; --l) {
+        const int c = chan(l), hl = u->h >> l, wl = u->w >> l;
+        const Layer &U = u->L[find(u, (std::string("u") + char('0' + l)).c_str())];
+        const Layer &A = u->L[find(u, (std::string("d") + char('0' + l) + "a").c_str())];
+        const Layer &B = u->L[find(u, (std::string("d") + char('0' + l) + "b").c_str())];
+        const uint16_t *in = l == LEVELS - 2 ? at<uint16_t>(u, y.eb3) : at<uint16_t>(u, y.db[l + 1]);
+        if ((e = launch_conv(in, chan(l + 1), chan(l + 1), wf + U.ow, th + U.ob, at<uint16_t>(u, y.ul[l]), c, c,
+                             nullptr, 0, n, hl / 2, wl / 2, 1, 0, s)) != hipSuccess) return e;
+        const long long items = (long long)n * (hl / 2) * (wl / 2) * (c / 8);
+        hipLaunchKernelGGL(k_upsample, dim3(nblocks(items)), dim3(WG), 0, s, (const uint16_t *)at<uint16_t>(u, y.ul[l]),
+                           c, at<uint16_t>(u, y.cat[l]) + c, 2 * c, c, n, hl / 2, wl / 2);
+        if ((e = launch_conv(at<uint16_t>(u, y.cat[l]), 2 * c, 2 * c, wf + A.ow, th + A.ob, at<uint16_t>(u, y.da[l]),
+                             c, c, nullptr, 0, n, hl, wl, 3, 1, s)) != hipSuccess) return e;
+        if ((e = launch_conv(at<uint16_t>(u, y.da[l]), c, c, wf + B.ow, th + B.ob, at<uint16_t>(u, y.db[l]), c, c,
+                             nullptr, 0, n, hl, wl, 3, 1, s)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+// the gradient of the loss (after forward) into y.grad, and the loss into `loss`
+static hipError_t backward(epidmc_unet *u, int n, double *loss, hipStream_t s)
+{
+    auto &y = u->lay;
+    const uint16_t *wb = at<uint16_t>(u, y.wb);
+    float *gr = at<float>(u, y.grad), *wgs = at<float>(u, y.wgs);
+    const long long hw = (long long)u->h * u->w, P = hw * n;
+    const Layer &H = u->L[NL - 1];
+    const long long hb = nblocks(P);
+    hipLaunchKernelGGL(k_head, dim3(hb), dim3(WG), 0, s, (const uint16_t *)at<uint16_t>(u, y.db[0]),
+                       (const float *)(at<float>(u, y.theta) + H.ow), (const float *)(at<float>(u, y.theta) + H.ob),
+                       (const float *)at<float>(u, y.x0), (const float *)at<float>(u, y.tgt), (const double *)at<double>(u, y.scale), hw, P,
+                       (double *)nullptr, at<uint16_t>(u, y.gdb[0]), at<float>(u, y.headpart));
+    hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(64), 0, s, (const float *)at<float>(u, y.headpart), (int)hb, P,
+                       gr + H.ow, gr + H.ob, loss);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int l = 0; l < LEVELS - 1; ++l) {
+        const int c = chan(l), hl = u->h >> l, wl = u->w >> l;
+        const Layer &U = u->L[find(u, (std::string("u") + char('0' + l)).c_str())];
+        const Layer &A = u->L[find(u, (std::string("d") + char('0' + l) + "a").c_str())];
+        const Layer &B = u->L[find(u, (std::string("d") + char('0' + l) + "b").c_str())];
+        // d{l}b
+        if ((e = launch_wgrad(at<uint16_t>(u, y.da[l]), c, c, at<uint16_t>(u, y.gdb[l]), c, c, n, hl, wl, 3,
+                              gr + B.ow, gr + B.ob, wgs, s)) != hipSuccess) return e;
+        if ((e = launch_conv(at<uint16_t>(u, y.gdb[l]), c, c, wb + B.ow, nullptr, at<uint16_t>(u, y.gda[l]), c, c,
+                             at<uint16_t>(u, y.da[l]), c, n, hl, wl, 3, 0, s)) != hipSuccess) return e;
+        // d{l}a: input is the concatenation [skip, upsampled]
+        if ((e = launch_wgrad(at<uint16_t>(u, y.cat[l]), 2 * c, 2 * c, at<uint16_t>(u, y.gda[l]), c, c, n, hl, wl, 3,
+                              gr + A.ow, gr + A.ob, wgs, s)) != hipSuccess) return e;
+        if ((e = launch_conv(at<uint16_t>(u, y.gda[l]), c, c, wb + A.ow, nullptr, at<uint16_t>(u, y.gcat[l]), 2 * c,
+                             2 * c, nullptr, 0, n, hl, wl, 3, 0, s)) != hipSuccess) return e;
+        // the upsampled half back to the 1x1 up-convolution's output
+        const long long items = (long long)n * (hl / 2) * (wl / 2) * (c / 8);
+        hipLaunchKernelGGL(k_upsample_bwd, dim3(nblocks(items)), dim3(WG), 0, s,
+                           (const uint16_t *)(at<uint16_t>(u, y.gcat[l]) + c), 2 * c, at<uint16_t>(u, y.gul[l]), c, c,
+                           n, hl, wl);
+        const uint16_t *in = l == LEVELS - 2 ? at<uint16_t>(u, y.eb3) : at<uint16_t>(u, y.db[l + 1]);
+        uint16_t *gin = l == LEVELS - 2 ? at<uint16_t>(u, y.geb[LEVELS - 1]) : at<uint16_t>(u, y.gdb[l + 1]);
+        const int c1 = chan(l + 1);
+        if ((e = launch_wgrad(in, c1, c1, at<uint16_t>(u, y.gul[l]), c, c, n, hl / 2, wl / 2, 1, gr + U.ow, gr + U.ob,
+                              wgs, s)) != hipSuccess) return e;
+        if ((e = launch_conv(at<uint16_t>(u, y.gul[l]), c, c, wb + U.ow, nullptr, gin, c1, c1, in, c1, n, hl / 2,
+                             wl / 2, 1, 0, s)) != hipSuccess) return e;
+    }
+    for (int l = LEVELS - 1; l >= 0; --l) {
+        const int c = chan(l), hl = u->h >> l, wl = u->w >> l;
+        const Layer &A = u->L[2 * l], &B = u->L[2 * l + 1];
+        const uint16_t *act_b = l < LEVELS - 1 ? at<uint16_t>(u, y.cat[l]) : at<uint16_t>(u, y.eb3);
+        const int ldb = l < LEVELS - 1 ? 2 * c : c;
+        if (l < LEVELS - 1) {
+            const long long items = (long long)n * hl * wl * (c / 8);
+            hipLaunchKernelGGL(k_skip_bwd, dim3(nblocks(items)), dim3(WG), 0, s,
+                               (const uint16_t *)at<uint16_t>(u, y.gcat[l]), 2 * c,
+                               (const uint16_t *)at<uint16_t>(u, y.gp[l]), c, act_b, ldb, at<uint16_t>(u, y.geb[l]), c,
+                               c, n, hl, wl);
+        }
+        if ((e = launch_wgrad(at<uint16_t>(u, y.ea[l]), c, c, at<uint16_t>(u, y.geb[l]), c, c, n, hl, wl, 3,
+                              gr + B.ow, gr + B.ob, wgs, s)) != hipSuccess) return e;
+        if ((e = launch_conv(at<uint16_t>(u, y.geb[l]), c, c, wb + B.ow, nullptr, at<uint16_t>(u, y.gea[l]), c, c,
+                             at<uint16_t>(u, y.ea[l]), c, n, hl, wl, 3, 0, s)) != hipSuccess) return e;
+        const uint16_t *in = l == 0 ? at<uint16_t>(u, y.X) : at<uint16_t>(u, y.pl[l - 1]);
+        const int ldin = l == 0 ? 8 : chan(l - 1);
+        if ((e = launch_wgrad(in, ldin, A.cin, at<uint16_t>(u, y.gea[l]), c, c, n, hl, wl, 3, gr + A.ow, gr + A.ob, wgs,
+                              s)) != hipSuccess) return e;
+        if (l > 0 && (e = launch_conv(at<uint16_t>(u, y.gea[l]), c, c, wb + A.ow, nullptr, at<uint16_t>(u, y.gp[l - 1]),
+                                      chan(l - 1), chan(l - 1), nullptr, 0, n, hl, wl, 3, 0, s)) != hipSuccess)
+            return e;
+    }
+    return hipGetLastError();
+}
+
+static epidmc_status check_batch(epidmc_unet *u, int n)
+{
+    UREQ(u->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    UREQ(u->have_params, EPIDMC_E_NOT_READY, "parameters not set");
+    UREQ(n >= 1 && n <= u->n, EPIDMC_E_SHAPE, "batch larger than the bound batch");
+    return EPIDMC_OK;
+}
+
+static epidmc_status conv_shape_ok(int ldx, int cin, int ldy, int cout, int n, int h, int w, int k)
+{
+    if (!(k == 1 || k == 3) || n < 0 || h < 0 || w < 0) return EPIDMC_E_ARG;
+    if (cin < 8 || cin % 8 || !pow2(cin / 8) || cout < 32 || cout % 32 || ldx < cin || ldx % 8 || ldy < cout ||
+        ldy % 8)
+        return EPIDMC_E_SHAPE;
+    return EPIDMC_OK;
+}
+
+}  // namespace dn
+
+// ---------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+epidmc_status epidmc_dn_conv(const uint16_t *x, int ldx, int c_in, const uint16_t *w, const float *bias, uint16_t *y,
+                             int ldy, int c_out, const uint16_t *gate, int ldg, int n, int h, int w_px, int k, int relu,
+                             void *stream)
+{
+    epidmc_status st = conv_shape_ok(ldx, c_in, ldy, c_out, n, h, w_px, k);
+    if (st != EPIDMC_OK) return st;
+    if (!x || !w || !y || (gate && (ldg < c_out || ldg % 8))) return EPIDMC_E_ARG;
+    return launch_conv(x, ldx, c_in, w, bias, y, ldy, c_out, gate, ldg, n, h, w_px, k, relu, (hipStream_t)stream) ==
+                   hipSuccess
+               ? EPIDMC_OK
+               : EPIDMC_E_DEVICE;
+}
+
+epidmc_status epidmc_dn_wgrad_scratch(int n, int h, int w_px, int k, int c_in, int c_out, size_t *floats)
+{
+    epidmc_status st = conv_shape_ok(c_in, c_in, c_out, c_out, n, h, w_px, k);
+    if (st != EPIDMC_OK || !floats) return st != EPIDMC_OK ? st : EPIDMC_E_ARG;
+    *floats = wgrad_plan((long long)n * h * w_px, k, c_in, c_out).floats;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_dn_wgrad(const uint16_t *x, int ldx, int c_in, const uint16_t *g, int ldg, int c_out, int n,
+                              int h, int w_px, int k, float *dw, float *db, float *scratch, size_t scratch_floats,
+                              void *stream)
+{
+    epidmc_status st = conv_shape_ok(ldx, c_in, ldg, c_out, n, h, w_px, k);
+    if (st != EPIDMC_OK) return st;
+    if (!x || !g || !dw || !scratch || (long long)n * h * w_px == 0) return EPIDMC_E_ARG;
+    if (scratch_floats < wgrad_plan((long long)n * h * w_px, k, c_in, c_out).floats) return EPIDMC_E_WORKSPACE;
+    return launch_wgrad(x, ldx, c_in, g, ldg, c_out, n, h, w_px, k, dw, db, scratch, (hipStream_t)stream) == hipSuccess
+               ? EPIDMC_OK
+               : EPIDMC_E_DEVICE;
+}
+
+epidmc_status epidmc_dn_weights(const float *w, int c_out, int k, int c_in, uint16_t *w_fwd, uint16_t *w_bwd,
+                                void *stream)
+{
+    if (!w || c_out < 1 || c_in < 1 || !(k == 1 || k == 3)) return EPIDMC_E_ARG;
+    const long long cnt = (long long)c_out * k * k * c_in;
+    hipLaunchKernelGGL(k_weights, dim3(nblocks(cnt)), dim3(WG), 0, (hipStream_t)stream, w, c_out, k * k, c_in, w_fwd,
+                       w_bwd);
+    return hipGetLastError() == hipSuccess ? EPIDMC_OK : EPIDMC_E_DEVICE;
+}
+
+static epidmc_status ew_ok(const void *a, const void *b, int lda, int ldb, int c, int n, int h, int w, bool even)
+{
+    if (!a || !b || c < 8 || c % 8 || lda < c || ldb < c || lda % 8 || ldb % 8 || n < 0 || h < 0 || w < 0)
+        return EPIDMC_E_ARG;
+    if (even && (h % 2 || w % 2)) return EPIDMC_E_SHAPE;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_dn_pool(const uint16_t *x, int ldx, uint16_t *y, int ldy, int c, int n, int h, int w_px,
+                             void *stream)
+{
+    epidmc_status st = ew_ok(x, y, ldx, ldy, c, n, h, w_px, true);
+    if (st != EPIDMC_OK) return st;
+    const long long items = (long long)n * (h / 2) * (w_px / 2) * (c / 8);
+    if (items == 0) return EPIDMC_OK;
+    hipLaunchKernelGGL(k_pool, dim3(nblocks(items)), dim3(WG), 0, (hipStream_t)stream, x, ldx, y, ldy, c, n, h, w_px);
+    return hipGetLastError() == hipSuccess ? EPIDMC_OK : EPIDMC_E_DEVICE;
+}
+
+epidmc_status epidmc_dn_upsample(const uint16_t *x, int ldx, uint16_t *y, int ldy, int c, int n, int h, int w_px,
+                                 void *stream)
+{
+    epidmc_status st = ew_ok(x, y, ldx, ldy, c, n, h, w_px, false);
+    if (st != EPIDMC_OK) return st;
+    const long long items = (long long)n * h * w_px * (c / 8);
+    if (items == 0) return EPIDMC_OK;
+    hipLaunchKernelGGL(k_upsample, dim3(nblocks(items)), dim3(WG), 0, (hipStream_t)stream, x, ldx, y, ldy, c, n, h,
+                       w_px);
+    return hipGetLastError() == hipSuccess ? EPIDMC_OK : EPIDMC_E_DEVICE;
+}
+
+epidmc_status epidmc_dn_upsample_backward(const uint16_t *g, int ldg, uint16_t *y, int ldy, int c, int n, int h,
+                                          int w_px, void *stream)
+{
+    epidmc_status st = ew_ok(g, y, ldg, ldy, c, n, h, w_px, true);
+    if (st != EPIDMC_OK) return st;
+    const long long items = (long long)n * (h / 2) * (w_px / 2) * (c / 8);
+    if (items == 0) return EPIDMC_OK;
+    hipLaunchKernelGGL(k_upsample_bwd, dim3(nblocks(items)), dim3(WG), 0, (hipStream_t)stream, g, ldg, y, ldy, c, n,
+                       h, w_px);
+    return hipGetLastError() == hipSuccess ? EPIDMC_OK : EPIDMC_E_DEVICE;
+}
+
+epidmc_status epidmc_dn_skip_backward(const uint16_t *g_skip, int lds, const uint16_t *g_pool, int ldp,
+                                      const uint16_t *act, int lda, uint16_t *out, int ldo, int c, int n, int h,
+                                      int w_px, void *stream)
+{
+    epidmc_status st = ew_ok(g_skip, out, lds, ldo, c, n, h, w_px, true);
+    if (st != EPIDMC_OK) return st;
+    st = ew_ok(g_pool, act, ldp, lda, c, n, h, w_px, true);
+    if (st != EPIDMC_OK) return st;
+    const long long items = (long long)n * h * w_px * (c / 8);
+    if (items == 0) return EPIDMC_OK;
+    hipLaunchKernelGGL(k_skip_bwd, dim3(nblocks(items)), dim3(WG), 0, (hipStream_t)stream, g_skip, lds, g_pool, ldp,
+                       act, lda, out, ldo, c, n, h, w_px);
+    return hipGetLastError() == hipSuccess ? EPIDMC_OK : EPIDMC_E_DEVICE;
+}
+
+epidmc_status epidmc_unet_create(epidmc_unet **out, int device)
+{
+    if (!out) return EPIDMC_E_ARG;
+    int nd = 0;
+    if (hipGetDeviceCount(&nd) != hipSuccess || device < 0 || device >= nd) return EPIDMC_E_DEVICE;
+    epidmc_unet *u = new epidmc_unet();
+    u->device = device;
+    make_layers(u);
+    *out = u;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_destroy(epidmc_unet *u)
+{
+    delete u;
+    return EPIDMC_OK;
+}
+
+const char *epidmc_unet_last_error(const epidmc_unet *u) { return u ? u->err.c_str() : "null context"; }
+
+int epidmc_unet_layers(const epidmc_unet *u) { return u ? NL : 0; }
+
+epidmc_status epidmc_unet_param_count(const epidmc_unet *u, size_t *floats)
+{
+    if (!u || !floats) return EPIDMC_E_ARG;
+    *floats = u->nparam;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_layer(const epidmc_unet *u, int layer, char name[8], int *k, int *c_in, int *c_out,
+                                size_t *off_w, size_t *off_b)
+{
+    if (!u || layer < 0 || layer >= NL) return EPIDMC_E_ARG;
+    const Layer &x = u->L[layer];
+    if (name) std::memcpy(name, x.name, 8);
+    if (k) *k = x.k;
+    if (c_in) *c_in = x.cin;
+    if (c_out) *c_out = x.cout;
+    if (off_w) *off_w = x.ow;
+    if (off_b) *off_b = x.ob;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_workspace_size(const epidmc_unet *u, int n, int h, int w_px, size_t *bytes)
+{
+    if (!u || !bytes) return EPIDMC_E_ARG;
+    if (n < 1 || h < 8 || w_px < 8 || h % 8 || w_px % 8) return fail(u, EPIDMC_E_SHAPE, "n >= 1, h and w multiples of 8");
+    epidmc_unet tmp = *u;
+    *bytes = plan(&tmp, n, h, w_px);
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_bind(epidmc_unet *u, void *dev_ptr, size_t bytes, int n, int h, int w_px, void *stream)
+{
+    if (!u) return EPIDMC_E_ARG;
+    UREQ(dev_ptr && ((uintptr_t)dev_ptr % 256) == 0, EPIDMC_E_ARG, "workspace must be 256-byte aligned");
+    UREQ(n >= 1 && h >= 8 && w_px >= 8 && h % 8 == 0 && w_px % 8 == 0, EPIDMC_E_SHAPE,
+         "n >= 1, h and w multiples of 8");
+    const size_t need = plan(u, n, h, w_px);
+    UREQ(bytes >= need, EPIDMC_E_WORKSPACE, "workspace too small");
+    UCHK(hipSetDevice(u->device));
+    u->ws = (char *)dev_ptr;
+    u->n = n; u->h = h; u->w = w_px;
+    hipStream_t s = (hipStream_t)stream;
+    const long long np = (long long)u->nparam;
+    for (const Buf *b : {&u->lay.theta, &u->lay.m, &u->lay.v, &u->lay.grad})
+        hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(np)), dim3(WG), 0, s, (float *)(u->ws + b->off), np, 0.0f);
+    UCHK(hipGetLastError());
+    UCHK(weights_all(u, s));
+    u->bound = true;
+    u->have_params = false;
+    u->t = 0;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_set_params(epidmc_unet *u, const float *dev_params, void *stream)
+{
+    if (!u) return EPIDMC_E_ARG;
+    UREQ(u->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    UREQ(dev_params, EPIDMC_E_ARG, "null parameters");
+    hipStream_t s = (hipStream_t)stream;
+    const long long np = (long long)u->nparam;
+    hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(np)), dim3(WG), 0, s, dev_params, at<float>(u, u->lay.theta), np);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(np)), dim3(WG), 0, s, at<float>(u, u->lay.m), np, 0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(np)), dim3(WG), 0, s, at<float>(u, u->lay.v), np, 0.0f);
+    UCHK(hipGetLastError());
+    UCHK(weights_all(u, s));
+    u->have_params = true;
+    u->t = 0;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_get_params(const epidmc_unet *u, float *dev_params, void *stream)
+{
+    if (!u || !dev_params) return EPIDMC_E_ARG;
+    UREQ(u->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    const long long np = (long long)u->nparam;
+    hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(np)), dim3(WG), 0, (hipStream_t)stream,
+                       (const float *)(u->ws + u->lay.theta.off), dev_params, np);
+    UCHK(hipGetLastError());
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_forward(epidmc_unet *u, const double *noisy, const double *thickness, double *out, int n,
+                                  void *stream)
+{
+    if (!u) return EPIDMC_E_ARG;
+    epidmc_status st = check_batch(u, n);
+    if (st != EPIDMC_OK) return st;
+    UREQ(noisy && thickness && out, EPIDMC_E_ARG, "null image");
+    UCHK(hipSetDevice(u->device));
+    hipStream_t s = (hipStream_t)stream;
+    UCHK(prepare(u, noisy, thickness, nullptr, n, s));
+    UCHK(forward(u, n, s));
+    const long long hw = (long long)u->h * u->w, P = hw * n;
+    const Layer &H = u->L[NL - 1];
+    hipLaunchKernelGGL(k_head, dim3(nblocks(P)), dim3(WG), 0, s, (const uint16_t *)at<uint16_t>(u, u->lay.db[0]),
+                       (const float *)(at<float>(u, u->lay.theta) + H.ow),
+                       (const float *)(at<float>(u, u->lay.theta) + H.ob), (const float *)at<float>(u, u->lay.x0),
+                       (const float *)nullptr, (const double *)at<double>(u, u->lay.scale), hw, P, out,
+                       (uint16_t *)nullptr, (float *)nullptr);
+    UCHK(hipGetLastError());
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_gradient(epidmc_unet *u, const double *noisy, const double *thickness, const double *target,
+                                   int n, float *dev_grad, double *loss, void *stream)
+{
+    if (!u) return EPIDMC_E_ARG;
+    epidmc_status st = check_batch(u, n);
+    if (st != EPIDMC_OK) return st;
+    UREQ(noisy && thickness && target, EPIDMC_E_ARG, "null image");
+    UCHK(hipSetDevice(u->device));
+    hipStream_t s = (hipStream_t)stream;
+    UCHK(prepare(u, noisy, thickness, target, n, s));
+    UCHK(forward(u, n, s));
+    UCHK(backward(u, n, loss, s));
+    if (dev_grad) {
+        const long long np = (long long)u->nparam;
+        hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(np)), dim3(WG), 0, s, (const float *)at<float>(u, u->lay.grad),
+                           dev_grad, np);
+        UCHK(hipGetLastError());
+    }
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_train_step(epidmc_unet *u, const double *noisy, const double *thickness,
+                                     const double *target, int n, float lr, double *loss, void *stream)
+{
+    if (!u) return EPIDMC_E_ARG;
+    UREQ(std::isfinite(lr) && lr >= 0.0f, EPIDMC_E_ARG, "learning rate must be finite and >= 0");
+    epidmc_status st = epidmc_unet_gradient(u, noisy, thickness, target, n, nullptr, loss, stream);
+    if (st != EPIDMC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    u->t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float bc1 = (float)(1.0 - std::pow(b1, u->t)), bc2 = (float)(1.0 - std::pow(b2, u->t));
+    const long long np = (long long)u->nparam;
+    hipLaunchKernelGGL(k_adam, dim3(nblocks(np)), dim3(WG), 0, s, at<float>(u, u->lay.theta),
+                       (const float *)at<float>(u, u->lay.grad), at<float>(u, u->lay.m), at<float>(u, u->lay.v), np, lr,
+                       (float)b1, (float)b2, 1e-8f, bc1, bc2);
+    UCHK(hipGetLastError());
+    UCHK(weights_all(u, s));
+    return EPIDMC_OK;
+}
+
+}  // extern "C"

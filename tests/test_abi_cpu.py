@@ -1,5 +1,5 @@
 """CPU checks of the C ABI boundary: the shared library loads without a GPU and exports
-every entry point include/epidmc.h declares; the Python binding mirrors the names; the
+every entry point include/*.h declares; the Python binding mirrors the names; the
 product package refuses to run without its HIP library (no CPU fallback)."""
 import ctypes as ct
 import os
@@ -10,12 +10,12 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "epidmc.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in ("epidmc.h", "epidmc_denoise.h")]
 LIB = os.path.join(ROOT, "paper_2510_24154_amd", "libepidmc.so")
 
 
 def declared():
-    txt = open(HEADER).read()
+    txt = "".join(open(h).read() for h in HEADERS)
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(epidmc_[a-z_]+)\s*\(", txt)))
 

@@ -155,3 +155,20 @@ def test_adam_closed_form_steps():
     # the moments themselves: m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2
     np.testing.assert_allclose(m, (1 - 0.9 ** 5) * g, rtol=1e-12)
     np.testing.assert_allclose(v, (1 - 0.999 ** 5) * g * g, rtol=1e-12)
+
+
+def test_bf16_rounding_model_sits_inside_the_gpu_gradient_tolerance():
+    """The rounding model (BF16 storage of activations and activation gradients, FP32
+    weight gradients) on the GPU gradient test's case: its distance from the FP64 oracle is
+    what the GPU kernels are expected to show, and it stays below the GPU test's bound
+    with a margin of 1.5."""
+    from tests import _bf16_model as M
+    from tests.test_gpu_denoise import GRAD_CASE, GRAD_TOL, net_case
+    P, noisy, th, target = net_case(**GRAD_CASE)
+    x, s = U.normalise(noisy, th)
+    y = target / s[:, None, None]
+    out, act = U.forward(P, x)
+    ref = U.backward(P, act, out, y)
+    G = M.gradients(P, x, y)
+    worst = max(np.linalg.norm(G[k] - ref[k][0]) / np.linalg.norm(ref[k][0]) for k in ref)
+    assert 0.001 < worst < GRAD_TOL / 1.5, worst
