@@ -251,3 +251,61 @@ class Unet:
         t = self.torch
         self._c(self.L.epidmc_unet_train_step(self.h, _p(noisy), _p(thickness), _p(target), noisy.shape[0],
                                               float(lr), _p(loss), _stream(t)), "train_step")
+
+
+# ---- training data and training --------------------------------------------------------
+def make_pairs(fields, n_low, n_high, seed=1, max_chunk=1 << 24, device=0, engine=None):
+    """Low- and high-count images and radiological-thickness maps of a list of field
+    configurations, each transported by the engine on the GPU.  Returns (low, high,
+    thickness), FP64 device tensors of shape (fields, npx_v, npx_u).  The low image takes
+    history ids [0, n_low) and the high one [n_low, n_low + n_high): independent
+    estimates of the same expected image."""
+    import torch
+    from . import Engine
+    eng = engine or Engine(device, seed)
+    low = high = th = None
+    for i, cfg in enumerate(fields):
+        eng.configure(cfg, batches=64, max_chunk=int(min(max_chunk, max(n_low, n_high))))
+        eng.bind()
+        eng.run(int(n_low))
+        a = eng.image()[0]
+        if low is None:
+            shape = (len(fields),) + tuple(a.shape)
+            low, high, th = (torch.empty(shape, dtype=torch.float64, device=a.device) for _ in range(3))
+        low[i] = a
+        eng.reset()
+        eng.run(int(n_high), first=int(n_low))
+        high[i] = eng.image()[0]
+        th[i] = eng.radiological_thickness()
+    torch.cuda.synchronize()
+    return low, high, th
+
+
+def train(net, low, high, th, steps, batch=8, crop=None, lr=1e-3, lr_end=1e-4, seed=0, report=None):
+    """Adam on random crops (crop x crop, aligned to 8 pixels) of random training images
+    with random horizontal and vertical flips; the learning rate falls from lr to lr_end on
+    a cosine.  Returns the per-step losses (host numpy)."""
+    import math
+    import torch
+    rng = np.random.default_rng(seed)
+    N, H, W = low.shape
+    ch, cw = (H, W) if crop is None else (min(crop, H), min(crop, W))
+    loss = torch.zeros(steps, dtype=torch.float64, device=low.device)
+    for it in range(steps):
+        idx = torch.as_tensor(rng.integers(0, N, batch), device=low.device)
+        r0 = 8 * int(rng.integers(0, (H - ch) // 8 + 1))
+        c0 = 8 * int(rng.integers(0, (W - cw) // 8 + 1))
+        parts = []
+        for t in (low, th, high):
+            x = t[idx, r0:r0 + ch, c0:c0 + cw]
+            parts.append(x)
+        if rng.random() < 0.5:
+            parts = [x.flip(1) for x in parts]
+        if rng.random() < 0.5:
+            parts = [x.flip(2) for x in parts]
+        parts = [x.contiguous() for x in parts]
+        a = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * it / max(1, steps - 1)))
+        net.train_step(parts[0], parts[1], parts[2], a, loss=loss[it:it + 1])
+        if report and (it + 1) % report == 0:
+            print(f"[denoiser] step {it + 1}/{steps} loss {float(loss[it]):.5g}", flush=True)
+    return loss.cpu().numpy()
