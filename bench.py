@@ -85,6 +85,138 @@ def smoothed_sigma_bar(eng, torch, k=15, thr=0.5):
     return float((v[sel].clamp_min(0).sqrt() / ms[sel]).mean())
 
 
+DN_LOW, DN_HIGH, DN_REF = 20_000_000, 2_000_000_000, 10_000_000_000
+DN_PLAIN = (2_000_000, 20_000_000, 200_000_000, 2_000_000_000)
+DN_FLOP = 0.2136e12   # forward FLOPs of the network per 1024 x 768 image (2 x multiply-adds)
+BF16_PEAK = 2.5e15    # dense BF16 MFMA, MI355X
+
+
+def denoiser_section(a, E, torch):
+    """Train the denoiser on engine-generated full-size fields (by default 2e7 histories
+    in, 2e9 as target), then on held-out fields compare the denoised low-count image and
+    plain images of 2e6..2e9 histories with a 1e10-history image on 8 x 8-binned pixels
+    (3.1 mm): 2%/2 mm gamma (global, 10% threshold) and the in-field relative RMSE, timing
+    each path end to end (transport, image, thickness map and network pass)."""
+    import numpy as np
+
+    from paper_2510_24154_amd import denoise as D
+    from paper_2510_24154_amd import synth
+    from tests._stats import gamma_pass, rebin
+    out = {}
+    sync = torch.cuda.synchronize
+    t = time.perf_counter()
+    fields = [synth.denoise_field(s) for s in range(a.dn_fields)]
+    n_low = int(a.dn_low)
+    low, high, th = D.make_pairs(fields, n_low, int(a.dn_target), seed=17, max_chunk=1 << 26, report=50)
+    out["input_histories"] = n_low
+    out["train_target_histories"] = int(a.dn_target)
+    out["train_fields"] = a.dn_fields
+    out["train_data_s"] = round(time.perf_counter() - t, 2)
+    print(f"[denoiser] {a.dn_fields} training pairs in {out['train_data_s']} s", file=sys.stderr, flush=True)
+    net = D.Unet(0).bind(8, 256, 256)
+    net.set_params(synth.unet_params(net.shapes(), seed=1, head_scale=0.01))
+    sync()
+    t = time.perf_counter()
+    losses = D.train(net, low, high, th, steps=a.dn_steps, batch=8, crop=256, lr=2e-3, lr_end=1e-4, seed=3,
+                     report=max(1, a.dn_steps // 4))
+    sync()
+    dt = time.perf_counter() - t
+    out["train_steps"] = a.dn_steps
+    out["train_s"] = round(dt, 2)
+    out["train_TFLOPs"] = round(3 * DN_FLOP * 8 * 65536 / 786432 * a.dn_steps / dt / 1e12, 1)
+    out["loss_first_last"] = [round(float(losses[:50].mean()), 4), round(float(losses[-50:].mean()), 4)]
+    del low, high, th
+    full = D.Unet(0).bind(1, 1024, 768)
+    full.set_params(net.get_params())
+    eng = E.Engine(0, seed=29)
+    rows = []
+    for i in range(a.dn_eval):
+        cfg = synth.denoise_field(100_000 + i)
+        eng.configure(cfg, batches=64, max_chunk=1 << 26)
+        eng.bind()
+        r = {}
+        # the denoised path: 2e6 histories, the thickness map, one network pass
+        for rep in range(2):   # the first pass warms the kernels up
+            eng.reset()
+            sync()
+            t = time.perf_counter()
+            eng.run(n_low, first=0)
+            img = eng.image()[0][None]
+            tk = eng.radiological_thickness()[None]
+            den = full.forward(img, tk)
+            sync()
+            r["denoised_s"] = time.perf_counter() - t
+        ev = {"denoised": den[0].cpu().numpy()}
+        first = n_low
+        for n in DN_PLAIN:
+            eng.reset()
+            sync()
+            t = time.perf_counter()
+            eng.run(n, first=first)
+            m = eng.image()[0]
+            sync()
+            r[f"plain_{n:.0e}_s"] = time.perf_counter() - t
+            ev[f"plain_{n:.0e}"] = m.cpu().numpy()
+            first += n
+        eng.reset()
+        eng.run(DN_REF, first=first)
+        ref = rebin(eng.image()[0].cpu().numpy(), 8)
+        sel = ref >= 0.1 * ref.max()
+        for k, v in ev.items():
+            b = rebin(v, 8)
+            r[f"gamma_{k}"] = gamma_pass(ref, b, 0.312, dd=0.02, dta=0.2, thr=0.10)
+            r[f"rmse_{k}"] = float(np.sqrt(np.mean((b[sel] - ref[sel]) ** 2)) / ref[sel].mean())
+        rows.append(r)
+        print(f"[denoiser] eval field {i}: " + ", ".join(f"{k} {v:.4g}" for k, v in r.items()), file=sys.stderr,
+              flush=True)
+    keys = rows[0].keys()
+    mean = {k: float(np.mean([r[k] for r in rows])) for k in keys}
+    out["eval_fields"] = a.dn_eval
+    out["gamma_2pct_2mm"] = {k[6:]: round(v, 4) for k, v in mean.items() if k.startswith("gamma_")}
+    out["in_field_rel_rmse"] = {k[5:]: round(v, 4) for k, v in mean.items() if k.startswith("rmse_")}
+    # plain histories giving the denoised RMSE: the 2e9 point's RMSE scaled by 1/sqrt(N)
+    # after removing the reference's own share (its variance adds to every comparison)
+    e_ref2 = 0.0
+    e2 = {n: mean[f"rmse_plain_{n:.0e}"] ** 2 for n in DN_PLAIN}
+    n_hi, n_lo = DN_PLAIN[-1], DN_PLAIN[-2]
+    # e2(N) = c / N + e_ref2, from the two largest plain counts
+    c = (e2[n_lo] - e2[n_hi]) / (1.0 / n_lo - 1.0 / n_hi)
+    e_ref2 = max(0.0, e2[n_hi] - c / n_hi)
+    d2 = mean["rmse_denoised"] ** 2 - e_ref2
+    if c > 0 and d2 > 0:
+        n_eq = c / d2
+        out["plain_histories_at_equal_rmse"] = float(f"{n_eq:.3g}")
+        rate = DN_PLAIN[-1] / mean[f"plain_{DN_PLAIN[-1]:.0e}_s"]   # measured plain histories/s
+        out["speedup_at_equal_rmse"] = round(n_eq / rate / mean["denoised_s"], 1)
+    out["reference_rmse_share"] = round(float(np.sqrt(e_ref2)), 4)
+    out["seconds"] = {k[:-2]: round(v, 4) for k, v in mean.items() if k.endswith("_s")}
+    # plain histories needed for the denoised pass rate: the smallest plain N that reaches it
+    g_den = mean["gamma_denoised"]
+    match = [n for n in DN_PLAIN if mean[f"gamma_plain_{n:.0e}"] >= g_den]
+    if match:
+        n = match[0]
+        out["plain_histories_at_equal_gamma"] = n
+        out["speedup_at_equal_gamma"] = round(mean[f"plain_{n:.0e}_s"] / mean["denoised_s"], 1)
+    else:
+        out["plain_histories_at_equal_gamma"] = f"> {DN_PLAIN[-1]:.0e}"
+        out["speedup_at_equal_gamma"] = f"> {mean[f'plain_{DN_PLAIN[-1]:.0e}_s'] / mean['denoised_s']:.1f}"
+    # inference throughput of the network alone
+    x = torch.as_tensor(np.asarray(ev["denoised"]))[None].cuda()
+    for _ in range(3):
+        full.forward(x, x)
+    sync()
+    t = time.perf_counter()
+    for _ in range(20):
+        full.forward(x, x)
+    sync()
+    f_ms = (time.perf_counter() - t) / 20 * 1e3
+    out["inference_ms"] = round(f_ms, 3)
+    out["roofline"] = {"bound": "mfma", "achieved": round(DN_FLOP / (f_ms * 1e-3) / 1e12, 1), "peak": 2500.0,
+                       "unit": "TFLOP/s", "frac": round(DN_FLOP / (f_ms * 1e-3) / BF16_PEAK, 4),
+                       "scope": "whole forward pass, 1024 x 768, BF16 MFMA"}
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +229,13 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--no-denoiser", action="store_true",
+                    help="skip training the denoiser on engine-generated fields and comparing it with plain MC")
+    ap.add_argument("--dn-fields", type=int, default=64)
+    ap.add_argument("--dn-steps", type=int, default=3000)
+    ap.add_argument("--dn-target", type=float, default=DN_HIGH)
+    ap.add_argument("--dn-low", type=float, default=DN_LOW)
+    ap.add_argument("--dn-eval", type=int, default=3)
     ap.add_argument("--t1-measured", action="store_true",
                     help="also run the coupled workload until sigma-bar <= 1% (about 80 s) and time it")
     return ap.parse_args()
@@ -220,6 +359,13 @@ def main():
                     "first_history": h}
         print(json.dumps({"t1pct_measured": measured}), file=sys.stderr, flush=True)
 
+    dn = None
+    if not a.no_denoiser:
+        try:
+            dn = denoiser_section(a, E, torch)
+        except Exception as e:   # the transport line above must still be reported
+            dn = {"error": f"{type(e).__name__}: {e}"}
+
     if a.calib_copy:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
@@ -269,6 +415,7 @@ def main():
         "cpu_baseline": cpu,
         "dose_response": response,
         "t1pct_measured": measured,
+        "denoiser": dn,
         "counters": {k: c[k] for k in ("woodcock_steps", "e_steps_phantom", "e_steps_epid", "epid_photon_steps",
                                        "tally_deposits", "launches", "kernel_ms", "kernel_launches",
                                        "queue_items", "lane_iters", "wave_iters")},

@@ -98,13 +98,13 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
     const int steps = (a.kg_total + 3) >> 2;
     const int cmask = (1 << a.cg_shift) - 1;
     const u32x4 zero = {0u, 0u, 0u, 0u};
-    for (int s = 0; s < steps; ++s) {
+    // operands of step s: A (4 pixel rows) and B (NT weight columns), zero past the end
+    auto load = [&](int s, u32x4 *A, u32x4 *B) {
         const int kg = s * 4 + grp;
         const bool kv = kg < a.kg_total;
         const int tap = kg >> a.cg_shift, cg = kg & cmask;
         const int dy = KS == 3 ? tap / 3 - 1 : 0;
         const int dx = KS == 3 ? tap - (tap / 3) * 3 - 1 : 0;
-        u32x4 A[4], B[NT];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int yy = py[m] + dy, xx = px[m] + dx;
@@ -118,10 +118,23 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
             const u32x4 v = *(const u32x4 *)(wrow[t] + (kv ? kg * 8 : 0));
             B[t] = kv ? v : zero;
         }
+    };
+    // two register stages: the loads of step s+1 are in flight during step s's MFMAs.  The
+    // step count is rounded up to even; a step past the end loads zeros.
+    const int steps2 = (steps + 1) & ~1;
+    u32x4 A0[4], B0[NT], A1[4], B1[NT];
+    load(0, A0, B0);
+    for (int s = 0; s < steps2; s += 2) {
+        load(s + 1, A1, B1);
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A0[m], B0[t], acc[m][t]);
+        load(s + 2 < steps2 ? s + 2 : s + 1, A0, B0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A1[m], B1[t], acc[m][t]);
     }
     // lane holds rows 4*grp + r of each 16-pixel tile, column `row` of each channel tile
 #pragma unroll
@@ -147,7 +160,8 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
 // ---------------------------------------------------------------------------------------
 struct WgArgs {
     const uint16_t *x, *g;
-    float *part, *dbpart;
+    float *part;
+    int with_db;
     long long P;
     int ldx, ldg, cin, cout, h, wd, cg_shift, kg_total, cols, cols_pad, chunk_px;
 };
@@ -170,7 +184,7 @@ __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
     const long long pc1 = min(pc0 + (long long)a.chunk_px, a.P);
     const int hw = a.h * a.wd;
     const int cmask = (1 << a.cg_shift) - 1;
-    const bool do_db = a.dbpart && blockIdx.y == 0;
+    const bool do_db = a.with_db && blockIdx.y == 0;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -227,7 +241,8 @@ __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
             for (int j = 0; j < 2; ++j) acc[i][j] = mfma(A[i], B[j], acc[i][j]);
         __syncthreads();
     }
-    float *dst = a.part + (size_t)blockIdx.z * a.cout * a.cols_pad;
+    const size_t R = (size_t)a.cout * a.cols_pad + a.cout;   // one row per pixel chunk: dw, then db
+    float *dst = a.part + (size_t)blockIdx.z * R;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -245,26 +260,38 @@ __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
         if (tid < TM) {   // channel co0 + tid = group c8 = tid / 8, element tid % 8
             float s = 0.0f;
             for (int pp = 0; pp < 32; ++pp) s += red[pp * (TM / 8) + tid / 8][tid % 8];
-            a.dbpart[(size_t)blockIdx.z * a.cout + co0 + tid] = s;
+            dst[(size_t)a.cout * a.cols_pad + co0 + tid] = s;
         }
     }
 }
 
-__global__ void k_wgrad_reduce(const float *part, const float *dbpart, int nchunk, int cout, int cols, int cols_pad,
-                               float *dw, float *db)
+// Sum of the pixel chunks' partial rows (R floats each) in a fixed order: stage 1 adds
+// groups of RG consecutive chunks (threads run along the row, so loads are coalesced),
+// stage 2 adds the groups and scatters the row into dw [cout][cols] and db [cout].
+constexpr int RG = 32;
+__global__ void k_wgrad_sum1(const float *part, long long R, int nchunk, float *stage)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long nw = (long long)cout * cols;
-    if (i < nw) {
-        const int co = (int)(i / cols), col = (int)(i - (long long)co * cols);
-        float s = 0.0f;
-        for (int c = 0; c < nchunk; ++c) s += part[((size_t)c * cout + co) * cols_pad + col];
-        dw[i] = s;
-    } else if (db && i < nw + cout) {
-        const int co = (int)(i - nw);
-        float s = 0.0f;
-        for (int c = 0; c < nchunk; ++c) s += dbpart[(size_t)c * cout + co];
-        db[co] = s;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= R) return;
+    const int c0 = blockIdx.y * RG, c1 = min(c0 + RG, nchunk);
+    float s = 0.0f;
+    for (int c = c0; c < c1; ++c) s += part[(size_t)c * R + e];
+    stage[(size_t)blockIdx.y * R + e] = s;
+}
+
+__global__ void k_wgrad_sum2(const float *stage, long long R, int ngroup, int cout, int cols, int cols_pad, float *dw,
+                             float *db)
+{
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= R) return;
+    float s = 0.0f;
+    for (int g = 0; g < ngroup; ++g) s += stage[(size_t)g * R + e];
+    const long long nw = (long long)cout * cols_pad;
+    if (e < nw) {
+        const int co = (int)(e / cols_pad), col = (int)(e - (long long)co * cols_pad);
+        if (col < cols) dw[(long long)co * cols + col] = s;
+    } else if (db) {
+        db[e - nw] = s;
     }
 }
 
@@ -467,16 +494,25 @@ __global__ __launch_bounds__(WG) void k_head(const uint16_t *t0, const float *wh
     }
 }
 
-// dw (HC floats), db, and loss = sum of squares / P, from the blocks' partials
-__global__ void k_head_reduce(const float *part, int nblk, long long P, float *dw, float *db, double *loss)
+// dw (HC floats), db, and loss = sum of squares / P from the blocks' partials: one block
+// per output, strided FP64 sums and a fixed-order tree
+__global__ __launch_bounds__(WG) void k_head_reduce(const float *part, int nblk, long long P, float *dw, float *db,
+                                                    double *loss)
 {
-    const int c = threadIdx.x;
-    if (c >= HC + 2) return;
+    __shared__ double sh[WG];
+    const int c = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (HC + 2) + c];
-    if (c < HC) dw[c] = (float)s;
-    else if (c == HC) db[0] = (float)s;
-    else if (loss) loss[0] = s / (double)P;
+    for (int b = threadIdx.x; b < nblk; b += WG) s += part[(size_t)b * (HC + 2) + c];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = WG / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x) return;
+    if (c < HC) dw[c] = (float)sh[0];
+    else if (c == HC) db[0] = (float)sh[0];
+    else if (loss) loss[0] = sh[0] / (double)P;
 }
 
 __global__ void k_adam(float *th, const float *g, float *m, float *v, long long n, float lr, float b1, float b2,
@@ -536,7 +572,9 @@ static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_
 
 struct WgPlan {
     int wm, tm, tn, cols, cols_pad, chunk_px, nchunk;
-    size_t floats;   // partials of dw and db
+    int ngroup;      // groups of RG chunks in the first reduction stage
+    size_t row;      // floats per chunk row (dw then db)
+    size_t floats;   // chunk rows and group rows
 };
 
 static WgPlan wgrad_plan(long long P, int k, int cin, int cout)
@@ -552,7 +590,9 @@ static WgPlan wgrad_plan(long long P, int k, int cin, int cout)
     c = std::max<long long>(256, (c + 31) / 32 * 32);
     q.chunk_px = (int)std::min<long long>(c, 1 << 20);
     q.nchunk = (int)std::max<long long>(1, (P + q.chunk_px - 1) / q.chunk_px);
-    q.floats = (size_t)q.nchunk * cout * q.cols_pad + (size_t)q.nchunk * cout;
+    q.row = (size_t)cout * q.cols_pad + cout;
+    q.ngroup = (q.nchunk + RG - 1) / RG;
+    q.floats = q.row * (size_t)(q.nchunk + q.ngroup);
     return q;
 }
 
@@ -562,7 +602,7 @@ static hipError_t launch_wgrad(const uint16_t *x, int ldx, int cin, const uint16
     const long long P = (long long)n * h * wd;
     const WgPlan q = wgrad_plan(P, k, cin, cout);
     WgArgs a;
-    a.x = x; a.g = g; a.part = scratch; a.dbpart = db ? scratch + (size_t)q.nchunk * cout * q.cols_pad : nullptr;
+    a.x = x; a.g = g; a.part = scratch; a.with_db = db != nullptr;
     a.P = P; a.ldx = ldx; a.ldg = ldg; a.cin = cin; a.cout = cout; a.h = h; a.wd = wd;
     a.cg_shift = ilog2(cin / 8); a.kg_total = k * k * cin / 8;
     a.cols = q.cols; a.cols_pad = q.cols_pad; a.chunk_px = q.chunk_px;
@@ -576,9 +616,12 @@ static hipError_t launch_wgrad(const uint16_t *x, int ldx, int cin, const uint16
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const long long tot = (long long)cout * q.cols + (db ? cout : 0);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblocks(tot)), dim3(WG), 0, s, (const float *)a.part,
-                       (const float *)a.dbpart, q.nchunk, cout, q.cols, q.cols_pad, dw, db);
+    float *stage = scratch + q.row * (size_t)q.nchunk;
+    const long long R = (long long)q.row;
+    hipLaunchKernelGGL(k_wgrad_sum1, dim3(nblocks(R), q.ngroup), dim3(WG), 0, s, (const float *)scratch, R, q.nchunk,
+                       stage);
+    hipLaunchKernelGGL(k_wgrad_sum2, dim3(nblocks(R)), dim3(WG), 0, s, (const float *)stage, R, q.ngroup, cout, q.cols,
+                       q.cols_pad, dw, db);
     return hipGetLastError();
 }
 
@@ -812,7 +855,7 @@ static hipError_t backward(epidmc_unet *u, int n, double *loss, hipStream_t s)
                        (const float *)(at<float>(u, y.theta) + H.ow), (const float *)(at<float>(u, y.theta) + H.ob),
                        (const float *)at<float>(u, y.x0), (const float *)at<float>(u, y.tgt), (const double *)at<double>(u, y.scale), hw, P,
                        (double *)nullptr, at<uint16_t>(u, y.gdb[0]), at<float>(u, y.headpart));
-    hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(64), 0, s, (const float *)at<float>(u, y.headpart), (int)hb, P,
+    hipLaunchKernelGGL(k_head_reduce, dim3(HC + 2), dim3(WG), 0, s, (const float *)at<float>(u, y.headpart), (int)hb, P,
                        gr + H.ow, gr + H.ob, loss);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -195,6 +195,10 @@ class Unet:
         self.shape = (n, h, w)
         return self
 
+    def shapes(self):
+        """(name, k, c_in, c_out) of every layer as the parameters travel (c_in = 2 first)."""
+        return [(nm, k, 2 if nm == "e0a" else ci, co) for nm, k, ci, co, _, _ in self.layers]
+
     def flat(self, params):
         """Flat FP32 parameter vector (host numpy) from {name: (W, b)}."""
         v = np.zeros(self.nparam, np.float32)
@@ -254,7 +258,7 @@ class Unet:
 
 
 # ---- training data and training --------------------------------------------------------
-def make_pairs(fields, n_low, n_high, seed=1, max_chunk=1 << 24, device=0, engine=None):
+def make_pairs(fields, n_low, n_high, seed=1, max_chunk=1 << 24, device=0, engine=None, report=None):
     """Low- and high-count images and radiological-thickness maps of a list of field
     configurations, each transported by the engine on the GPU.  Returns (low, high,
     thickness), FP64 device tensors of shape (fields, npx_v, npx_u).  The low image takes
@@ -277,6 +281,8 @@ def make_pairs(fields, n_low, n_high, seed=1, max_chunk=1 << 24, device=0, engin
         eng.run(int(n_high), first=int(n_low))
         high[i] = eng.image()[0]
         th[i] = eng.radiological_thickness()
+        if report and (i + 1) % report == 0:
+            print(f"[denoiser] {i + 1}/{len(fields)} fields transported", flush=True)
     torch.cuda.synchronize()
     return low, high, th
 
