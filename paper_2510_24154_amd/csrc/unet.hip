@@ -155,6 +155,86 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
     }
 }
 
+// 3x3 convolution with LDS tiles (c_in a multiple of 32): a workgroup owns an 8 x 32 pixel
+// tile of one image and NT*16 output channels.  Per step of 32 input channels it stages the
+// 10 x 34 input patch (halo included, zeros outside the image) and the weight slab
+// [NT*16][9 taps][32], then every wave (2 rows x 32 columns = 4 row tiles) runs the 9 taps
+// from LDS.  Row pitches of 80 and 592 bytes make the 16-byte reads of 16 lanes fall on
+// distinct banks.
+constexpr int TLH = 8, TLW = 32, PH = TLH + 2, PW = TLW + 2;
+constexpr int XP = 40;          // bf16 per staged pixel (32 channels + pad)
+constexpr int WP = 9 * 32 + 8;  // bf16 per staged output channel (9 taps x 32 + pad)
+
+template <int NT>
+__global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
+{
+    __shared__ __align__(16) uint16_t Xs[PH * PW * XP];
+    __shared__ __align__(16) uint16_t Ws[NT * 16 * WP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = lane & 15, grp = lane >> 4;
+    const int ty0 = (blockIdx.x / tiles_x) * TLH, tx0 = (blockIdx.x % tiles_x) * TLW;
+    const int img = blockIdx.y;
+    const int co0 = blockIdx.z * NT * 16;
+    const long long ibase = (long long)img * a.h * a.wd;
+    const int kstride = 9 * a.cin;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (int c0 = 0; c0 < a.cin; c0 += 32) {
+        for (int it = tid; it < PH * PW * 4; it += WG) {
+            const int q = it >> 2, g = it & 3;
+            const int y = ty0 + q / PW - 1, x = tx0 + q % PW - 1;
+            const bool ok = y >= 0 && y < a.h && x >= 0 && x < a.wd;
+            const long long off = ok ? (ibase + (long long)y * a.wd + x) * a.ldx + c0 + g * 8 : 0;
+            const u32x4 v = *(const u32x4 *)(a.x + off);
+            *(u32x4 *)(Xs + q * XP + g * 8) = ok ? v : zero;
+        }
+        for (int it = tid; it < NT * 16 * 36; it += WG) {
+            const int co = it / 36, r = it % 36, tap = r >> 2, g = r & 3;
+            *(u32x4 *)(Ws + co * WP + tap * 32 + g * 8) =
+                *(const u32x4 *)(a.w + (long long)(co0 + co) * kstride + tap * a.cin + c0 + g * 8);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap - dy * 3;
+            u32x4 A[4], B[NT];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int q = (2 * wave + (m >> 1) + dy) * PW + (m & 1) * 16 + row + dx;
+                A[m] = *(const u32x4 *)(Xs + q * XP + grp * 8);
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) B[t] = *(const u32x4 *)(Ws + (t * 16 + row) * WP + tap * 32 + grp * 8);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = co0 + t * 16 + row;
+        const float b = a.bias ? a.bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int y = ty0 + 2 * wave + (m >> 1), x = tx0 + (m & 1) * 16 + grp * 4 + r;
+                if (y >= a.h || x >= a.wd) continue;
+                const long long p = ibase + (long long)y * a.wd + x;
+                float v = acc[m][t][r] + b;
+                if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.gate && !(bf2f(a.gate[p * a.ldg + co]) > 0.0f)) v = 0.0f;
+                a.y[p * a.ldy + co] = f2bf(v);
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // backward-weights convolution
 // ---------------------------------------------------------------------------------------
@@ -559,6 +639,13 @@ static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_
     a.kg_total = k * k * cin / 8;
     if (a.P == 0) return hipSuccess;
     const bool wide = cout % 64 == 0;
+    if (k == 3 && cin % 32 == 0) {
+        const int tx = (wd + TLW - 1) / TLW, ty = (h + TLH - 1) / TLH;
+        dim3 grid(tx * ty, n, cout / (wide ? 64 : 32));
+        if (wide) hipLaunchKernelGGL((k_conv3_lds<4>), grid, dim3(WG), 0, s, a, tx);
+        else hipLaunchKernelGGL((k_conv3_lds<2>), grid, dim3(WG), 0, s, a, tx);
+        return hipGetLastError();
+    }
     dim3 grid(nblocks(a.P, 256), cout / (wide ? 64 : 32));
     if (k == 3) {
         if (wide) hipLaunchKernelGGL((k_conv<3, 4>), grid, dim3(WG), 0, s, a);
