@@ -247,16 +247,32 @@ struct WgArgs {
 };
 
 // Block tile: TM = 32 * WM output channels x TN = 32 * (4 / WM) columns; each wave a 32 x 32
-// sub-tile (2 x 2 MFMA tiles).  Per 32-pixel step the block stages g (pixels x channels)
-// and the shifted input (pixels x columns) into LDS transposed, so that a lane's operand is
-// 8 consecutive pixels of one row.
+// sub-tile (2 x 2 MFMA tiles).  Per step of KP = 128 pixels the block stages g (pixels x
+// channels) and the shifted input (pixels x columns) into LDS transposed, so that a lane's
+// operand is 8 consecutive pixels of one row.  Each staging item is an 8-pixel x 8-channel
+// block: eight 16-byte loads, a register transpose (byte permutes) and eight 16-byte LDS
+// stores.
+constexpr int KP = 128, KPP = KP + 8;   // pixels per step; LDS row pitch (272 bytes)
+
+// out[j] = channel j of pixels 0..7, two pixels per word, from in[p] = pixel p's 8 channels
+__device__ __forceinline__ void transpose8(const u32x4 in[8], u32x4 out[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int w = c >> 1;
+        const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;   // high or low halves
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[c][q] = __builtin_amdgcn_perm(in[2 * q + 1][w], in[2 * q][w], sel);
+    }
+}
+
 template <int KS, int WM>
 __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
 {
-    constexpr int TM = 32 * WM, TN = 32 * (4 / WM), PITCH = 40;   // 80-byte rows
-    __shared__ __align__(16) uint16_t Gt[TM * PITCH];
-    __shared__ __align__(16) uint16_t Xt[TN * PITCH];
-    __shared__ float red[WG][9];
+    constexpr int TM = 32 * WM, TN = 32 * (4 / WM);
+    __shared__ __align__(16) uint16_t Gt[TM * KPP];
+    __shared__ __align__(16) uint16_t Xt[TN * KPP];
+    __shared__ float red[KP / 8][TM];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int co0 = blockIdx.x * TM, col0 = blockIdx.y * TN;
@@ -273,52 +289,65 @@ __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
     float dbacc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) dbacc[j] = 0.0f;
-    constexpr int GI = 32 * TM / 8, XI = 32 * TN / 8;   // 16-byte items per tile
-    for (long long pb = pc0; pb < pc1; pb += 32) {
-        if (tid < GI) {
-            const int pp = tid / (TM / 8), c8 = tid % (TM / 8);
-            const long long p = pb + pp;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (p < pc1) v = *(const u32x4 *)(a.g + p * a.ldg + co0 + c8 * 8);
+    constexpr int GI = (KP / 8) * (TM / 8), XI = (KP / 8) * (TN / 8);   // 8 x 8 items per tile
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    for (long long pb = pc0; pb < pc1; pb += KP) {
+        if (tid < GI) {   // item: pixel group pg, channel group c8 (fixed per thread)
+            const int pg = tid / (TM / 8), c8 = tid % (TM / 8);
+            u32x4 in[8], out[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                Gt[(c8 * 8 + 2 * j) * PITCH + pp] = (uint16_t)(v[j] & 0xFFFFu);
-                Gt[(c8 * 8 + 2 * j + 1) * PITCH + pp] = (uint16_t)(v[j] >> 16);
-                dbacc[2 * j] += lo(v[j]);
-                dbacc[2 * j + 1] += hi(v[j]);
+            for (int j = 0; j < 8; ++j) {
+                const long long p = pb + pg * 8 + j;
+                const bool ok = p < pc1;
+                const u32x4 v = *(const u32x4 *)(a.g + (ok ? p * a.ldg + co0 + c8 * 8 : 0));
+                in[j] = ok ? v : zero;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) { dbacc[2 * q] += lo(in[j][q]); dbacc[2 * q + 1] += hi(in[j][q]); }
             }
+            transpose8(in, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u32x4 *)(Gt + (c8 * 8 + c) * KPP + pg * 8) = out[c];
         }
         for (int it = tid; it < XI; it += WG) {
-            const int pp = it / (TN / 8), kl = it % (TN / 8);
+            const int pg = it / (TN / 8), kl = it % (TN / 8);
             const int kg = col0 / 8 + kl;
-            const long long p = pb + pp;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (p < pc1 && kg < a.kg_total) {
-                const int tap = kg >> a.cg_shift, cg = kg & cmask;
-                const int n = (int)(p / hw), r = (int)(p - (long long)n * hw);
-                const int y = r / a.wd + (KS == 3 ? tap / 3 - 1 : 0);
-                const int x = r % a.wd + (KS == 3 ? tap % 3 - 1 : 0);
-                if (y >= 0 && y < a.h && x >= 0 && x < a.wd)
-                    v = *(const u32x4 *)(a.x + ((long long)n * hw + (long long)y * a.wd + x) * a.ldx + cg * 8);
-            }
+            const bool kv = kg < a.kg_total;
+            const int tap = kg >> a.cg_shift, cg = kg & cmask;
+            const int dy = KS == 3 ? tap / 3 - 1 : 0, dx = KS == 3 ? tap % 3 - 1 : 0;
+            u32x4 in[8], out[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                Xt[(kl * 8 + 2 * j) * PITCH + pp] = (uint16_t)(v[j] & 0xFFFFu);
-                Xt[(kl * 8 + 2 * j + 1) * PITCH + pp] = (uint16_t)(v[j] >> 16);
+            for (int j = 0; j < 8; ++j) {
+                const long long p = pb + pg * 8 + j;
+                bool ok = kv && p < pc1;
+                long long off = 0;
+                if (ok) {
+                    const int n = (int)(p / hw), r = (int)(p - (long long)n * hw);
+                    const int y = r / a.wd + dy, x = r % a.wd + dx;
+                    ok = y >= 0 && y < a.h && x >= 0 && x < a.wd;
+                    off = ((long long)n * hw + (long long)y * a.wd + x) * a.ldx + cg * 8;
+                }
+                const u32x4 v = *(const u32x4 *)(a.x + (ok ? off : 0));
+                in[j] = ok ? v : zero;
             }
+            transpose8(in, out);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u32x4 *)(Xt + (kl * 8 + c) * KPP + pg * 8) = out[c];
         }
         __syncthreads();
-        u32x4 A[2], B[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            A[i] = *(const u32x4 *)(Gt + (wm * 32 + i * 16 + (lane & 15)) * PITCH + 8 * (lane >> 4));
+        for (int ks = 0; ks < KP / 32; ++ks) {
+            u32x4 A[2], B[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-            B[j] = *(const u32x4 *)(Xt + (wn * 32 + j * 16 + (lane & 15)) * PITCH + 8 * (lane >> 4));
+            for (int i = 0; i < 2; ++i)
+                A[i] = *(const u32x4 *)(Gt + (wm * 32 + i * 16 + (lane & 15)) * KPP + ks * 32 + 8 * (lane >> 4));
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                B[j] = *(const u32x4 *)(Xt + (wn * 32 + j * 16 + (lane & 15)) * KPP + ks * 32 + 8 * (lane >> 4));
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = mfma(A[i], B[j], acc[i][j]);
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma(A[i], B[j], acc[i][j]);
+        }
         __syncthreads();
     }
     const size_t R = (size_t)a.cout * a.cols_pad + a.cout;   // one row per pixel chunk: dw, then db
@@ -334,13 +363,16 @@ __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
                 dst[(size_t)co * a.cols_pad + col] = acc[i][j][r];
             }
     if (do_db) {
+        if (tid < GI) {
+            const int pg = tid / (TM / 8), c8 = tid % (TM / 8);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) red[tid][j] = dbacc[j];
+            for (int j = 0; j < 8; ++j) red[pg][c8 * 8 + j] = dbacc[j];
+        }
         __syncthreads();
-        if (tid < TM) {   // channel co0 + tid = group c8 = tid / 8, element tid % 8
-            float s = 0.0f;
-            for (int pp = 0; pp < 32; ++pp) s += red[pp * (TM / 8) + tid / 8][tid % 8];
-            dst[(size_t)a.cout * a.cols_pad + co0 + tid] = s;
+        if (tid < TM) {
+            float sum = 0.0f;
+            for (int pg = 0; pg < KP / 8; ++pg) sum += red[pg][tid];
+            dst[(size_t)a.cout * a.cols_pad + co0 + tid] = sum;
         }
     }
 }
@@ -674,7 +706,7 @@ static WgPlan wgrad_plan(long long P, int k, int cin, int cout)
     q.cols_pad = (q.cols + q.tn - 1) / q.tn * q.tn;
     const long long tiles = (long long)(cout / q.tm) * (q.cols_pad / q.tn);
     long long c = (P * tiles + 2047) / 2048;           // about 2048 blocks in all
-    c = std::max<long long>(256, (c + 31) / 32 * 32);
+    c = std::max<long long>(256, (c + KP - 1) / KP * KP);
     q.chunk_px = (int)std::min<long long>(c, 1 << 20);
     q.nchunk = (int)std::max<long long>(1, (P + q.chunk_px - 1) / q.chunk_px);
     q.row = (size_t)cout * q.cols_pad + cout;
