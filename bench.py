@@ -227,6 +227,8 @@ def parse():
                     help="histories per step (default: the workload's; a segmented field is rescaled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the history chunk size by timing the candidates that fit (instead of 2^27)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-denoiser", action="store_true",
@@ -264,7 +266,13 @@ def main():
         cfg = synth.large_anthropomorphic()
     if segmented and n_step != n_default:
         cfg = synth.with_histories_scaled(cfg, n_step)
-    eng = E.Engine(0, seed=1).configure(cfg, batches=BATCHES, max_chunk=min(CHUNK, n_step))
+    chunk, tuned = CHUNK, None
+    if a.autotune:
+        from paper_2510_24154_amd.autotune import tune_chunk
+        chunk, rates = tune_chunk(cfg, n_step, seed=1, batches=BATCHES)
+        tuned = {str(k): round(v, 1) for k, v in rates.items()}
+        print(f"[autotune] histories/s by chunk: {tuned}; chosen {chunk}", file=sys.stderr, flush=True)
+    eng = E.Engine(0, seed=1).configure(cfg, batches=BATCHES, max_chunk=min(chunk, n_step))
     eng.bind()
     eng.set_profiling(True)
     h = 0
@@ -405,7 +413,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "name": a.workload,
                    "histories_per_step": n_step, "batches": BATCHES, "tally": "fp64",
-                   "first_history": first, "chunk": min(CHUNK, n_step)},
+                   "first_history": first, "chunk": min(chunk, n_step), "autotune": tuned},
         "s_to_1pct_extrapolated": round(t1_s, 2) if t1_s else None,
         "s_to_1pct_extrapolated_raw_selection": round(t1, 2) if t1 else None,
         "sigma_bar_smoothed_selection": round(sb_s, 5),

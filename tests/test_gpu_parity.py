@@ -297,3 +297,14 @@ def test_run_until_stops_at_target(E):
     done, sb = eng.run_until(0.05, thr=0.5, step=2_000_000, max_hist=200_000_000)
     assert sb <= 0.05 and done <= 200_000_000
     assert eng.sigma_bar(0.5) == pytest.approx(sb)
+
+
+def test_autotuner_times_the_candidates_that_fit(E):
+    from paper_2510_24154_amd.autotune import tune_chunk
+    cfg = synth.coupled_hetero_small()
+    best, rates = tune_chunk(cfg, 2_000_000, candidates=(1 << 16, 1 << 18, 1 << 20, 1 << 22, 1 << 26))
+    print("autotune:", rates, "best", best)
+    assert best in rates and rates[best] == max(rates.values())
+    assert set(rates) >= {1 << 16, 1 << 18, 1 << 20}
+    assert (1 << 26) not in rates   # more than twice the histories per run
+    assert all(v > 0 for v in rates.values())
