@@ -317,3 +317,47 @@ def test_trained_denoiser_beats_plain_monte_carlo(D):
     print(f"in-field relative RMSE: plain {e_plain:.4f}, plain x4 {e_4x:.4f}, denoised {e_den:.4f}")
     assert e_den < 0.5 * e_plain
     assert e_den < e_4x
+
+
+# ---- edge cases and error behaviour ------------------------------------------------------------
+def test_boundary_rejects_bad_shapes_and_states(D):
+    import torch
+    from paper_2510_24154_amd import EpidmcError
+    net = D.Unet(0)
+    with pytest.raises(EpidmcError, match="E_SHAPE"):
+        net.bind(1, 20, 24)                    # rows not a multiple of 8
+    net.bind(2, 16, 24)
+    z = torch.zeros((2, 16, 24), dtype=torch.float64, device="cuda")
+    with pytest.raises(EpidmcError, match="E_NOT_READY"):
+        net.forward(z, z)                      # parameters not set
+    net.set_params(synth.unet_params(U.layer_shapes(), seed=2))
+    z3 = torch.zeros((3, 16, 24), dtype=torch.float64, device="cuda")
+    with pytest.raises(EpidmcError, match="E_SHAPE"):
+        net.forward(z3, z3)                    # batch larger than the bound one
+    x = torch.zeros((1, 8, 8, 32), dtype=torch.bfloat16, device="cuda")
+    w = torch.zeros((16, 3, 3, 32), dtype=torch.bfloat16, device="cuda")
+    y = torch.zeros((1, 8, 8, 16), dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(EpidmcError, match="E_SHAPE"):
+        D.conv(x, w, None, y, 3)               # 16 output channels: not a multiple of 32
+    import ctypes as ct
+    lib = D._lib()
+    g = torch.zeros((1, 8, 8, 32), dtype=torch.bfloat16, device="cuda")
+    dw = torch.zeros((32, 3, 3, 32), dtype=torch.float32, device="cuda")
+    scratch = torch.zeros(16, dtype=torch.float32, device="cuda")
+    rc = lib.epidmc_dn_wgrad(D._p(x), 32, 32, D._p(g), 32, 32, 1, 8, 8, 3, D._p(dw), None, D._p(scratch), 16,
+                             ct.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == -5                            # EPIDMC_E_WORKSPACE: scratch too small
+
+
+def test_empty_image_uses_unit_scale(D):
+    """An all-zero low-count image has no mean to divide by: both sides take s = 1, and the
+    output is the learned correction alone."""
+    import torch
+    P, _, th, _ = net_case(n=1, seed=8)
+    noisy = np.zeros((1, 16, 24))
+    net = D.Unet(0).bind(1, 16, 24)
+    net.set_params(P)
+    dev = net.forward(torch.as_tensor(noisy).cuda(), torch.as_tensor(th).cuda()).cpu().numpy()
+    ref = U.denoise(P, noisy, th)
+    assert np.all(np.isfinite(dev))
+    assert rel_l2(dev, ref) < 0.03
