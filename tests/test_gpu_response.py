@@ -175,3 +175,22 @@ def test_large_case_transport_energy_ledger(E):
     assert c["max_ledger_resid"] < 1e-9
     m, v = eng.image()
     assert bool(np.isfinite(m.cpu().numpy()).all()) and float(m.sum()) > 0
+
+
+def test_dose_response_64x64_lut_matches_oracle(E, orc):
+    """The large case's correction table: 64 thickness nodes over 0-40 cm by 64 field-size
+    nodes over 2-25 cm (a smooth seeded k), bilinear and clamped, against the oracle."""
+    import torch
+    rng = np.random.default_rng(64)
+    t_nodes = np.linspace(0.0, 40.0, 64)
+    s_nodes = np.linspace(2.0, 25.0, 64)
+    T, S = np.meshgrid(t_nodes, s_nodes)
+    k = 1.0 + 0.05 * np.sin(T / 7.0) * np.cos(S / 5.0) + 0.01 * rng.standard_normal((64, 64))
+    cfg = synth.kerma_water(npx=64, pitch=0.5)
+    eng = engine_for(E, cfg)
+    th = rng.uniform(-5.0, 45.0, (64, 64))
+    img = rng.uniform(0.0, 2.0, (64, 64))
+    for s in (1.0, 2.0, 9.37, 25.0, 30.0):
+        out = eng.dose_response(torch.as_tensor(img), torch.as_tensor(th), s, t_nodes, s_nodes, k).cpu().numpy()
+        ref = img * orc.response_factor(t_nodes, s_nodes, k, th, s)
+        assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref)), s
