@@ -70,6 +70,8 @@ WORKLOADS = {
                "as coupled, 3e8 histories per step", 300_000_000),
     "large60": ("60-segment field on a 512x512x200 anthropomorphic-like phantom of 1 mm voxels, "
                 "4-layer EPID 1024x768, 2e9 histories per step", 2_000_000_000),
+    "imrt40_2p5mm": ("the 40-segment IMRT-like field scaled to 1e9 histories onto a 160x160 image of 2.5 mm "
+                     "pixels (the pixel pitch and history count the paper quotes its timing at)", 1_000_000_000),
 }
 
 
@@ -262,6 +264,8 @@ def main():
         cfg = synth.coupled_hetero()
     elif a.workload == "imrt40":
         cfg = synth.imrt_field()
+    elif a.workload == "imrt40_2p5mm":
+        cfg = synth.with_histories_scaled(synth.imrt_field(npx=(160, 160), pitch=0.25), n_default)
     else:
         cfg = synth.large_anthropomorphic()
     if segmented and n_step != n_default:
