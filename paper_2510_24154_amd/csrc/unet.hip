@@ -183,21 +183,48 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const u32x4 zero = {0u, 0u, 0u, 0u};
-    for (int c0 = 0; c0 < a.cin; c0 += 32) {
-        for (int it = tid; it < PH * PW * 4; it += WG) {
+    // the next step's patch and weights are loaded into registers while the current step's
+    // MFMAs run, and stored to LDS after the barrier
+    constexpr int XI = PH * PW * 4, XN = (XI + WG - 1) / WG;
+    constexpr int WI = NT * 16 * 36, WN = (WI + WG - 1) / WG;
+    u32x4 xr[XN], wr[WN];
+    auto gload = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < XN; ++k) {
+            const int it = tid + k * WG;
             const int q = it >> 2, g = it & 3;
             const int y = ty0 + q / PW - 1, x = tx0 + q % PW - 1;
-            const bool ok = y >= 0 && y < a.h && x >= 0 && x < a.wd;
+            const bool ok = it < XI && y >= 0 && y < a.h && x >= 0 && x < a.wd;
             const long long off = ok ? (ibase + (long long)y * a.wd + x) * a.ldx + c0 + g * 8 : 0;
             const u32x4 v = *(const u32x4 *)(a.x + off);
-            *(u32x4 *)(Xs + q * XP + g * 8) = ok ? v : zero;
+            xr[k] = ok ? v : zero;
         }
-        for (int it = tid; it < NT * 16 * 36; it += WG) {
+#pragma unroll
+        for (int k = 0; k < WN; ++k) {
+            const int it = tid + k * WG;
             const int co = it / 36, r = it % 36, tap = r >> 2, g = r & 3;
-            *(u32x4 *)(Ws + co * WP + tap * 32 + g * 8) =
-                *(const u32x4 *)(a.w + (long long)(co0 + co) * kstride + tap * a.cin + c0 + g * 8);
+            const bool ok = it < WI;
+            const long long off = ok ? (long long)(co0 + co) * kstride + tap * a.cin + c0 + g * 8 : 0;
+            wr[k] = *(const u32x4 *)(a.w + off);
+        }
+    };
+    gload(0);
+    for (int c0 = 0; c0 < a.cin; c0 += 32) {
+#pragma unroll
+        for (int k = 0; k < XN; ++k) {
+            const int it = tid + k * WG;
+            if (it < XI) *(u32x4 *)(Xs + (it >> 2) * XP + (it & 3) * 8) = xr[k];
+        }
+#pragma unroll
+        for (int k = 0; k < WN; ++k) {
+            const int it = tid + k * WG;
+            if (it < WI) {
+                const int co = it / 36, r = it % 36;
+                *(u32x4 *)(Ws + co * WP + (r >> 2) * 32 + (r & 3) * 8) = wr[k];
+            }
         }
         __syncthreads();
+        if (c0 + 32 < a.cin) gload(c0 + 32);
 #pragma unroll 1
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap - dy * 3;
