@@ -377,8 +377,10 @@ epidmc_status epidmc_set_segments(epidmc_ctx *c, int n_seg, int n_pairs, float l
     }
     uint64_t tot = 0;
     if (n_seg > 1)
-        for (int s = 0; s < n_seg; ++s) tot += n_hist[s];
-    REQUIRE(tot <= (1ull << 32), EPIDMC_E_RANGE, "history ids must stay below 2^32");
+        for (int s = 0; s < n_seg; ++s) {
+            REQUIRE(tot + n_hist[s] >= tot, EPIDMC_E_RANGE, "segment history counts overflow 64 bits");
+            tot += n_hist[s];
+        }
     c->n_seg = n_seg;
     c->n_pairs = n_pairs;
     c->leaf_w = leaf_w;

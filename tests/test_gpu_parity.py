@@ -308,3 +308,28 @@ def test_autotuner_times_the_candidates_that_fit(E):
     assert set(rates) >= {1 << 16, 1 << 18, 1 << 20}
     assert (1 << 26) not in rates   # more than twice the histories per run
     assert all(v > 0 for v in rates.values())
+
+
+def test_segmented_field_beyond_2_32_histories(E):
+    """A field whose segment counts sum past 2^32: histories from id 2^32 fall in the second
+    segment, so they give exactly (fixed point) the image of a one-segment field with that
+    segment's aperture over the same ids."""
+    cfg = synth.coupled_hetero_small()
+    ap = cfg["source"]["aperture"]
+    n_pairs = ap["a"].shape[1]
+    a2, b2 = ap["a"].copy(), ap["b"].copy()
+    a2[0, : n_pairs // 2] = 0.0          # the second segment: the field's lower half only
+    b2[0, : n_pairs // 2] = 0.0
+    two = copy.deepcopy(cfg)
+    two["source"]["aperture"] = dict(ap, a=np.concatenate([ap["a"], a2]), b=np.concatenate([ap["b"], b2]),
+                                     counts=np.array([1 << 32, 300_000], np.uint64))
+    one = copy.deepcopy(cfg)
+    one["source"]["aperture"] = dict(ap, a=a2, b=b2, counts=np.array([0], np.uint64))
+    imgs = []
+    for c in (two, one):
+        eng = E.Engine(0, seed=17).configure(c, tally=1, batches=4, max_chunk=1 << 17)
+        eng.bind()
+        eng.run(300_000, first=1 << 32)
+        imgs.append(eng.image()[0].cpu().numpy())
+    assert imgs[0].sum() > 0
+    np.testing.assert_array_equal(imgs[0], imgs[1])
