@@ -28,7 +28,7 @@ CHUNK = 1 << 27   # one chunk per 1e8-history step: fewer queue passes and launc
 # peak plain-ALU issue rate of MI355X: 256 CUs x 64 lanes x 2.4 GHz (one VALU op per lane per
 # clock; FMA and packed FP32 doubling excluded because the hot path is not FMA-bound)
 ALU_PEAK_OPS = 256 * 64 * 2.4e9
-# algorithmic VALU lane-operations per unit of work ("Roofline")
+# algorithmic VALU lane-operations per unit of work, counted from the step formulas
 OPS_PER_UNIT = {"electron_step": 310, "woodcock_step": 120, "epid_photon_step": 130}
 KIND = ["photon_phantom", "electron_phantom", "photon_epid", "electron_epid"]
 KERNEL = ["k_photon_phantom", "k_electron<phantom>", "k_photon_epid", "k_electron<epid>"]
@@ -291,7 +291,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; a run on N GPUs would shard histories "
-                                   "by id and all-reduce the tallies (see DESIGN.md), which is not built"}))
+                                   "by id and all-reduce the tallies, which is not built"}))
         sys.exit(2)
     import numpy as np
     import torch

@@ -7,7 +7,7 @@
  * hard collisions, continuous slowing down for soft ones); cut-offs 10 keV (photons)
  * and 200 keV (electrons); a voxelised density matrix derived from HU; a multi-layer
  * EPID (Sec. 2.1.3) scored on a 2D pixel grid (Sec. 2.3.3).  Every model detail the
- * paper leaves open is fixed by a stated reading (the design doc lists them); this file
+ * paper leaves open is fixed by an explicit reading shared with the engine; this file
  * implements those readings as plainly as possible:
  *   - cross sections are computed from their formulas at every energy (no tables);
  *   - photons are tracked voxel by voxel (Amanatides-Woo), not by delta tracking;

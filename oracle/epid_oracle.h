@@ -13,7 +13,7 @@
  *     of 10 keV for photons and 200 keV for electrons (Sec. 2.1.2);
  *   - electrons: the Class II condensed-history scheme of Sec. 2.1.2 (discrete
  *     hard collisions, continuous slowing down for soft ones), with the step
- *     rules fixed in the readings listed in the design doc;
+ *     rules fixed by explicit readings shared with the engine;
  *   - geometry: a voxelised density matrix (Sec. 2.1.2) followed by a stack of
  *     EPID layers (copper build-up, reflector, Gd2O2S phosphor, protective
  *     layers; Sec. 2.1.3) with a 2D pixel grid in the scoring layer.

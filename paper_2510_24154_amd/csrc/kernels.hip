@@ -6,8 +6,8 @@
 // iteration, and appends secondaries and region changes to next-pass queues with one
 // atomic per wave.  Cross-section tables are staged in LDS once per workgroup.
 //
-// Physics per step (the paper's physics class, Sec. 2.1.2, with the model readings
-// documented in the design doc):
+// Physics per step (the paper's physics class, Sec. 2.1.2; where the paper leaves a model
+// open, the engine and the CPU oracle implement the same explicit reading):
 //   photons in the phantom: Woodcock delta tracking against a per-energy majorant;
 //   photons in the EPID: exact slab-by-slab tracking (Sec. 2.1.3);
 //   interactions: Compton (Klein-Nishina, Butcher-Messel composition-rejection),
