@@ -108,6 +108,10 @@ struct epidmc_ctx {
     // profiling
     int prof = 0;
     hipEvent_t ev[2][NQ] = {};
+    // one stream per particle kind: the kinds of a pass run concurrently, so a pass lasts
+    // as long as its slowest kernel rather than the sum of them
+    hipStream_t ks[NQ] = {};
+    hipEvent_t go = nullptr, done[NQ] = {};
     double kernel_ms[NQ] = {0, 0, 0, 0};
     uint64_t kernel_launches[NQ] = {0, 0, 0, 0};
     // accumulated
@@ -161,6 +165,11 @@ epidmc_status epidmc_destroy(epidmc_ctx *c)
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < NQ; ++k)
             if (c->ev[b][k]) (void)hipEventDestroy(c->ev[b][k]);
+    for (int k = 0; k < NQ; ++k) {
+        if (c->done[k]) (void)hipEventDestroy(c->done[k]);
+        if (c->ks[k]) (void)hipStreamDestroy(c->ks[k]);
+    }
+    if (c->go) (void)hipEventDestroy(c->go);
     if (c->host) (void)hipHostFree(c->host);
     delete c;
     return EPIDMC_OK;
@@ -792,8 +801,23 @@ static uint64_t batch_start(uint64_t first, uint64_t n, int B, uint64_t b)
     return first + (b * n + (uint64_t)B - 1) / (uint64_t)B;
 }
 
+static epidmc_status kind_streams(epidmc_ctx *c)
+{
+    if (c->go) return EPIDMC_OK;
+    for (int k = 0; k < NQ; ++k) {
+        HIPCHK(hipStreamCreateWithFlags(&c->ks[k], hipStreamNonBlocking));   // default priority
+        HIPCHK(hipEventCreateWithFlags(&c->done[k], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&c->go, hipEventDisableTiming));
+    return EPIDMC_OK;
+}
+
 static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStream_t s)
 {
+    {
+        const epidmc_status st = kind_streams(c);
+        if (st != EPIDMC_OK) return st;
+    }
     Params P = c->P;
     P.h0 = h0;
     P.h1 = h1;
@@ -845,17 +869,24 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
         HIPCHK(launch_zero(seg + (1 - cur) * SEG_SET, SEG_SET * 4, s));
         HIPCHK(launch_zero(seg + 2 * SEG_SET, SEG_SET * 4, s));
         use(cur);
+        // the pass's kernels start together once the counters are cleared, each on its
+        // kind's stream; the run stream waits for all of them before the next pass
+        HIPCHK(hipEventRecord(c->go, s));
         for (int k = 0; k < NQ; ++k) {
             if (!n[k]) continue;
             const uint64_t per_block = (uint64_t)WG * ITEMS_PER_LANE;
             const uint64_t want = (n[k] + per_block - 1) / per_block;
             const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * c->occ[k]));
-            if (c->prof) HIPCHK(hipEventRecord(c->ev[0][k], s));
-            HIPCHK(launch_transport(k, P, blocks, s));
+            hipStream_t ks = c->ks[k];
+            HIPCHK(hipStreamWaitEvent(ks, c->go, 0));
+            if (c->prof) HIPCHK(hipEventRecord(c->ev[0][k], ks));
+            HIPCHK(launch_transport(k, P, blocks, ks));
             if (c->prof) {
-                HIPCHK(hipEventRecord(c->ev[1][k], s));
+                HIPCHK(hipEventRecord(c->ev[1][k], ks));
                 timed[k] = true;
             }
+            HIPCHK(hipEventRecord(c->done[k], ks));
+            HIPCHK(hipStreamWaitEvent(s, c->done[k], 0));
             ++c->launches;
         }
         cur = 1 - cur;
