@@ -241,6 +241,20 @@ class Unet:
         self._c(self.L.epidmc_unet_forward(self.h, _p(noisy), _p(thickness), _p(out), n, _stream(t)), "forward")
         return out
 
+    def capture_forward(self, noisy, thickness, out):
+        """Record one forward pass over these (fixed) FP64 device tensors into a HIP graph and
+        return it; graph.replay() then re-runs the whole pass (about 30 kernels) with one
+        launch.  The pass issues kernels only (no memory set, copy or synchronisation), so
+        it can be captured; refresh the tensors' contents in place between replays."""
+        t = self.torch
+        n = noisy.shape[0]
+        t.cuda.synchronize()
+        g = t.cuda.CUDAGraph()
+        with t.cuda.graph(g):
+            self._c(self.L.epidmc_unet_forward(self.h, _p(noisy), _p(thickness), _p(out), n, _stream(t)),
+                    "forward")
+        return g
+
     def gradient(self, noisy, thickness, target):
         """(loss, {name: (dW, db)}) for a batch (FP64 device tensors (n, h, w))."""
         t = self.torch

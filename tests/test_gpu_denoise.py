@@ -361,3 +361,27 @@ def test_empty_image_uses_unit_scale(D):
     ref = U.denoise(P, noisy, th)
     assert np.all(np.isfinite(dev))
     assert rel_l2(dev, ref) < 0.03
+
+
+def test_forward_replays_from_a_hip_graph(D):
+    """The forward pass captured once and replayed: every replay, with new inputs written in
+    place and eager work between replays, gives the eager result bit for bit."""
+    import torch
+    P, noisy, th, _ = net_case(n=2, h=32, w=48, seed=12)
+    net = D.Unet(0).bind(2, 32, 48)
+    net.set_params(P)
+    x = torch.as_tensor(noisy).cuda()
+    t = torch.as_tensor(th).cuda()
+    out = torch.empty_like(x)
+    g = net.capture_forward(x, t, out)
+    rng = np.random.default_rng(12)
+    for rep in range(4):
+        x.copy_(torch.as_tensor(rng.gamma(2.0, 1e-5, noisy.shape)))
+        t.copy_(torch.as_tensor(rng.uniform(5, 30, th.shape)))
+        g.replay()
+        torch.cuda.synchronize()
+        replayed = out.clone()
+        eager = net.forward(x, t)          # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(replayed, eager), rep
+        assert float(replayed.abs().sum()) > 0
