@@ -107,7 +107,9 @@ def denoiser_section(a, E, torch):
     out = {}
     sync = torch.cuda.synchronize
     t = time.perf_counter()
-    fields = [synth.denoise_field(s) for s in range(a.dn_fields)]
+    fields = [synth.denoise_field(s, mixed=bool(a.dn_mixed)) for s in range(a.dn_fields)]
+    out["train_recipe"] = "mixed: single-segment ellipsoid fields and multi-segment thorax fields" if a.dn_mixed \
+        else "single-segment ellipsoid fields"
     n_low = int(a.dn_low)
     low, high, th = D.make_pairs(fields, n_low, int(a.dn_target), seed=17, max_chunk=1 << 26, report=50)
     out["input_histories"] = n_low
@@ -210,6 +212,11 @@ def denoiser_section(a, E, torch):
             b = rebin(v, 8)
             lg["gamma_2pct_2mm"][k] = round(gamma_pass(ref, b, 0.312, dd=0.02, dta=0.2, thr=0.10), 4)
             lg["in_field_rel_rmse"][k] = round(float(np.sqrt(np.mean((b[sel] - ref[sel]) ** 2)) / ref[sel].mean()), 4)
+        n_eq, sp, _ = equal_rmse(lg["in_field_rel_rmse"], lg["seconds"], lg["in_field_rel_rmse"]["denoised"],
+                                 lg["seconds"]["denoised"])
+        if n_eq:
+            lg["plain_histories_at_equal_rmse"] = float(f"{n_eq:.3g}")
+            lg["speedup_at_equal_rmse"] = round(sp, 1)
         out["large_case"] = lg
         print(f"[denoiser] large case: {lg}", file=sys.stderr, flush=True)
     keys = rows[0].keys()
@@ -217,20 +224,13 @@ def denoiser_section(a, E, torch):
     out["eval_fields"] = a.dn_eval
     out["gamma_2pct_2mm"] = {k[6:]: round(v, 4) for k, v in mean.items() if k.startswith("gamma_")}
     out["in_field_rel_rmse"] = {k[5:]: round(v, 4) for k, v in mean.items() if k.startswith("rmse_")}
-    # plain histories giving the denoised RMSE: the 2e9 point's RMSE scaled by 1/sqrt(N)
-    # after removing the reference's own share (its variance adds to every comparison)
-    e_ref2 = 0.0
-    e2 = {n: mean[f"rmse_plain_{n:.0e}"] ** 2 for n in DN_PLAIN}
-    n_hi, n_lo = DN_PLAIN[-1], DN_PLAIN[-2]
-    # e2(N) = c / N + e_ref2, from the two largest plain counts
-    c = (e2[n_lo] - e2[n_hi]) / (1.0 / n_lo - 1.0 / n_hi)
-    e_ref2 = max(0.0, e2[n_hi] - c / n_hi)
-    d2 = mean["rmse_denoised"] ** 2 - e_ref2
-    if c > 0 and d2 > 0:
-        n_eq = c / d2
+    # plain histories giving the denoised RMSE, after removing the reference's own share
+    rm = {k[5:]: v for k, v in mean.items() if k.startswith("rmse_")}
+    secs = {k[:-2]: v for k, v in mean.items() if k.endswith("_s")}
+    n_eq, sp, e_ref2 = equal_rmse(rm, secs, mean["rmse_denoised"], mean["denoised_s"])
+    if n_eq:
         out["plain_histories_at_equal_rmse"] = float(f"{n_eq:.3g}")
-        rate = DN_PLAIN[-1] / mean[f"plain_{DN_PLAIN[-1]:.0e}_s"]   # measured plain histories/s
-        out["speedup_at_equal_rmse"] = round(n_eq / rate / mean["denoised_s"], 1)
+        out["speedup_at_equal_rmse"] = round(sp, 1)
     out["reference_rmse_share"] = round(float(np.sqrt(e_ref2)), 4)
     out["seconds"] = {k[:-2]: round(v, 4) for k, v in mean.items() if k.endswith("_s")}
     # plain histories needed for the denoised pass rate: the smallest plain N that reaches it
@@ -271,6 +271,22 @@ def denoiser_section(a, E, torch):
     return out
 
 
+def equal_rmse(rmse, seconds, denoised_rmse, denoised_s):
+    """Plain histories with the denoised image's RMSE, and the wall-clock speedup: RMSE^2 =
+    c / N + e_ref^2 fitted through the two largest plain counts (e_ref^2 is the reference's
+    own share, common to every comparison), the plain rate from the largest run."""
+    n_hi, n_lo = DN_PLAIN[-1], DN_PLAIN[-2]
+    e2_hi, e2_lo = rmse[f"plain_{n_hi:.0e}"] ** 2, rmse[f"plain_{n_lo:.0e}"] ** 2
+    c = (e2_lo - e2_hi) / (1.0 / n_lo - 1.0 / n_hi)
+    e_ref2 = max(0.0, e2_hi - c / n_hi)
+    d2 = denoised_rmse ** 2 - e_ref2
+    if c <= 0 or d2 <= 0:
+        return None, None, e_ref2
+    n_eq = c / d2
+    rate = n_hi / seconds[f"plain_{n_hi:.0e}"]
+    return n_eq, n_eq / rate / denoised_s, e_ref2
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,12 +303,14 @@ def parse():
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-denoiser", action="store_true",
                     help="skip training the denoiser on engine-generated fields and comparing it with plain MC")
-    ap.add_argument("--dn-fields", type=int, default=64)
+    ap.add_argument("--dn-fields", type=int, default=96)
     ap.add_argument("--dn-steps", type=int, default=3000)
     ap.add_argument("--dn-target", type=float, default=DN_HIGH)
     ap.add_argument("--dn-low", type=float, default=DN_LOW)
     ap.add_argument("--dn-eval", type=int, default=3)
     ap.add_argument("--dn-large", type=int, default=1, help="also judge the denoiser on the large case (0: skip)")
+    ap.add_argument("--dn-mixed", type=int, default=1,
+                    help="1: every other training field is a thorax-like phantom under a multi-segment field")
     ap.add_argument("--t1-measured", action="store_true",
                     help="also run the coupled workload until sigma-bar <= 1% (about 80 s) and time it")
     return ap.parse_args()

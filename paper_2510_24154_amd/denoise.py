@@ -275,15 +275,25 @@ class Unet:
 def make_pairs(fields, n_low, n_high, seed=1, max_chunk=1 << 24, device=0, engine=None, report=None):
     """Low- and high-count images and radiological-thickness maps of a list of field
     configurations, each transported by the engine on the GPU.  Returns (low, high,
-    thickness), FP64 device tensors of shape (fields, npx_v, npx_u).  The low image takes
-    history ids [0, n_low) and the high one [n_low, n_low + n_high): independent
-    estimates of the same expected image."""
+    thickness), FP64 device tensors of shape (fields, npx_v, npx_u).  For a one-segment
+    field the low image takes history ids [0, n_low) and the high one [n_low, n_low +
+    n_high); a field of several segments is delivered whole at each count, by two engines
+    of different seeds.  Either way the two are independent estimates of the same expected
+    image."""
     import torch
-    from . import Engine
+    from . import Engine, synth
     eng = engine or Engine(device, seed)
+    eng_hi = None
     low = high = th = None
+    chunk = int(min(max_chunk, max(n_low, n_high)))
     for i, cfg in enumerate(fields):
-        eng.configure(cfg, batches=64, max_chunk=int(min(max_chunk, max(n_low, n_high))))
+        segmented = np.asarray(cfg["source"]["aperture"]["a"]).shape[0] > 1
+        if segmented:
+            # a field of several segments is delivered whole at each count: the low image
+            # by one engine, the high one by a second engine with another seed
+            eng.configure(synth.with_histories_scaled(cfg, int(n_low)), batches=64, max_chunk=chunk)
+        else:
+            eng.configure(cfg, batches=64, max_chunk=chunk)
         eng.bind()
         eng.run(int(n_low))
         a = eng.image()[0]
@@ -291,10 +301,18 @@ def make_pairs(fields, n_low, n_high, seed=1, max_chunk=1 << 24, device=0, engin
             shape = (len(fields),) + tuple(a.shape)
             low, high, th = (torch.empty(shape, dtype=torch.float64, device=a.device) for _ in range(3))
         low[i] = a
-        eng.reset()
-        eng.run(int(n_high), first=int(n_low))
-        high[i] = eng.image()[0]
         th[i] = eng.radiological_thickness()
+        if segmented:
+            if eng_hi is None:
+                eng_hi = Engine(device, seed + 7919)
+            eng_hi.configure(synth.with_histories_scaled(cfg, int(n_high)), batches=64, max_chunk=chunk)
+            eng_hi.bind()
+            eng_hi.run(int(n_high))
+            high[i] = eng_hi.image()[0]
+        else:
+            eng.reset()
+            eng.run(int(n_high), first=int(n_low))
+            high[i] = eng.image()[0]
         if report and (i + 1) % report == 0:
             print(f"[denoiser] {i + 1}/{len(fields)} fields transported", flush=True)
     torch.cuda.synchronize()

@@ -314,11 +314,52 @@ def random_aperture(rng, n_pairs=60, leaf_w=0.5, max_gap=10.0, n_hist=1):
             "a": a[None, :], "b": b[None, :], "counts": np.array([n_hist], np.uint64)}
 
 
-def denoise_field(seed, shape=(128, 128, 64), spacing=0.4, npx=(768, 1024), pitch=0.039):
+def thorax_hu(rng, shape=(128, 128, 50), spacing=0.4):
+    """int16 HU grid (x fastest) of a seeded thorax-like phantom for a beam along +z: the
+    large case's body (an elliptic cylinder of soft tissue with a skin shell, two lungs, a
+    spine; air outside) with every size and position drawn around its values: body
+    semi-axes 17 x 9.5 cm x U(0.8, 1.1), lungs at x = -/+8 cm + U(-2, 2), semi-axes
+    (5.5, 12, 5.5) cm x U(0.7, 1.2), spine radius 1.8 cm x U(0.8, 1.2) at z offset
+    6 cm + U(-1, 1)."""
+    nx, ny, nz = shape
+    x = (np.arange(nx) + 0.5) * spacing - 0.5 * nx * spacing
+    y = (np.arange(ny) + 0.5) * spacing - 0.5 * ny * spacing
+    z = (np.arange(nz) + 0.5) * spacing - 0.5 * nz * spacing
+    X, Y, Z = x[None, None, :], y[None, :, None], z[:, None, None]
+    bx, bz = 17.0 * rng.uniform(0.8, 1.1), 9.5 * rng.uniform(0.8, 1.1)
+    hu = np.full((nz, ny, nx), -1000, dtype=np.int16)
+    hu[np.broadcast_to((X / bx) ** 2 + (Z / bz) ** 2 <= 1.0, hu.shape)] = 60
+    hu[np.broadcast_to((X / (bx - 0.3)) ** 2 + (Z / (bz - 0.3)) ** 2 <= 1.0, hu.shape)] = 40
+    for side in (-1.0, 1.0):
+        cx = side * 8.0 + rng.uniform(-2.0, 2.0)
+        ax = np.array([5.5, 12.0, 5.5]) * rng.uniform(0.7, 1.2, 3)
+        cz = -1.0 + rng.uniform(-1.0, 1.0)
+        hu[((X - cx) / ax[0]) ** 2 + (Y / ax[1]) ** 2 + ((Z - cz) / ax[2]) ** 2 <= 1.0] = -750
+    r = 1.8 * rng.uniform(0.8, 1.2)
+    hu[np.broadcast_to(X ** 2 + (Z - 6.0 - rng.uniform(-1.0, 1.0)) ** 2 <= r * r, hu.shape)] = 800
+    return hu.reshape(-1)
+
+
+def denoise_field(seed, shape=(128, 128, 64), spacing=0.4, npx=(768, 1024), pitch=0.039, mixed=False):
     """A training or evaluation field for the denoiser: the coupled workload's source and
     EPID with a seeded ellipsoid phantom (4 mm voxels by default) and one seeded MLC
-    segment.  Returns a workload configuration."""
+    segment.  With mixed=True every odd seed instead gives a seeded thorax-like phantom
+    (128 x 128 x 50 voxels of 4 mm, the large case's extents) under a field of 5-20 seeded
+    segments with uneven counts (relative counts; deliver it with with_histories_scaled).
+    Returns a workload configuration."""
     rng = np.random.default_rng(10_000 + seed)
+    if mixed and seed % 2 == 1:
+        cfg = coupled_hetero(shape=(8, 8, 8), npx=npx, pitch=pitch)
+        tshape, sp = (128, 128, 50), (0.4, 0.4, 0.4)
+        origin = (-0.5 * tshape[0] * sp[0], -0.5 * tshape[1] * sp[1], 100.0 - 0.5 * tshape[2] * sp[2])
+        cfg["phantom"] = {"kind": "hu", "shape": tshape, "spacing": sp, "origin": origin,
+                          "hu": thorax_hu(rng, tshape, sp[0]),
+                          "curve": copy.deepcopy(HU_CURVE), "ranges": copy.deepcopy(HU_RANGES)}
+        n_seg = int(rng.integers(5, 21))
+        cfg["source"]["aperture"] = mlc_segments(n_seg=n_seg, total=1_000_000 * n_seg, aperture_seed=30_000 + seed,
+                                                 count_seed=40_000 + seed, lo=200_000, hi=5_000_000)
+        cfg["name"] = f"denoise_field_{seed}_thorax"
+        return cfg
     cfg = coupled_hetero(shape=shape, spacing=spacing, npx=npx, pitch=pitch, phantom_seed=20_000 + seed)
     cfg["name"] = f"denoise_field_{seed}"
     cfg["source"]["aperture"] = random_aperture(rng)

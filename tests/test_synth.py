@@ -38,3 +38,22 @@ def test_mlc_segments_counts():
     assert n.sum() == 300_000_000 and n.min() >= 1_000_000 and n.max() <= 50_000_000
     assert ap["a"].shape == (40, 60) and (ap["b"] >= ap["a"]).all()
     assert np.all(ap["b"] - ap["a"] <= 10.0)
+
+
+def test_mixed_denoiser_fields():
+    """Even seeds keep the single-segment ellipsoid field; odd seeds of the mixed recipe give
+    a thorax-like phantom of the large case's extents under 5-20 segments."""
+    from paper_2510_24154_amd import synth
+    even = synth.denoise_field(4, mixed=True)
+    assert even["source"]["aperture"]["a"].shape[0] == 1
+    odd = synth.denoise_field(5, mixed=True)
+    ph = odd["phantom"]
+    assert ph["shape"] == (128, 128, 50) and ph["spacing"] == (0.4, 0.4, 0.4)
+    assert set(np.unique(ph["hu"])) <= {-1000, -750, 40, 60, 800}
+    assert (ph["hu"] == -750).sum() > 0 and (ph["hu"] == 800).sum() > 0
+    ap = odd["source"]["aperture"]
+    n_seg = ap["a"].shape[0]
+    assert 5 <= n_seg <= 20 and int(ap["counts"].sum()) == 1_000_000 * n_seg
+    # the same seed gives the same field
+    again = synth.denoise_field(5, mixed=True)
+    assert np.array_equal(again["phantom"]["hu"], ph["hu"]) and np.array_equal(again["source"]["aperture"]["a"], ap["a"])
