@@ -119,6 +119,8 @@ def denoiser_section(a, E, torch):
     print(f"[denoiser] {a.dn_fields} training pairs in {out['train_data_s']} s", file=sys.stderr, flush=True)
     net = D.Unet(0).bind(8, 256, 256)
     net.set_params(synth.unet_params(net.shapes(), seed=1, head_scale=0.01))
+    net.set_ema(a.dn_ema)
+    out["weight_ema_decay"] = a.dn_ema
     sync()
     t = time.perf_counter()
     losses = D.train(net, low, high, th, steps=a.dn_steps, batch=8, crop=256, lr=2e-3, lr_end=1e-4, seed=3,
@@ -131,7 +133,7 @@ def denoiser_section(a, E, torch):
     out["loss_first_last"] = [round(float(losses[:50].mean()), 4), round(float(losses[-50:].mean()), 4)]
     del low, high, th
     full = D.Unet(0).bind(1, 1024, 768)
-    full.set_params(net.get_params())
+    full.set_params(net.get_ema_params() if a.dn_ema > 0 else net.get_params())
     eng = E.Engine(0, seed=29)
     rows = []
     for i in range(a.dn_eval):
@@ -309,6 +311,8 @@ def parse():
     ap.add_argument("--dn-low", type=float, default=DN_LOW)
     ap.add_argument("--dn-eval", type=int, default=3)
     ap.add_argument("--dn-large", type=int, default=1, help="also judge the denoiser on the large case (0: skip)")
+    ap.add_argument("--dn-ema", type=float, default=0.0,
+                    help="decay of the moving average of the weights used for inference (0: the last weights)")
     ap.add_argument("--dn-mixed", type=int, default=1,
                     help="1: every other training field is a thorax-like phantom under a multi-segment field")
     ap.add_argument("--t1-measured", action="store_true",

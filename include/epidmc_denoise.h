@@ -112,6 +112,13 @@ epidmc_status epidmc_unet_bind(epidmc_unet *u, void *dev_ptr, size_t bytes, int 
 epidmc_status epidmc_unet_set_params(epidmc_unet *u, const float *dev_params, void *stream);
 epidmc_status epidmc_unet_get_params(const epidmc_unet *u, float *dev_params, void *stream);
 
+/* Exponential moving average of the weights during training: with decay d in (0, 1), each
+ * Adam step also sets ema <- d * ema + (1 - d) * theta; 0 (the default) turns it off.
+ * set_params resets the average to the loaded parameters.  get_ema_params copies it out
+ * (device pointer, param_count floats), e.g. to load it into an inference runner. */
+epidmc_status epidmc_unet_set_ema(epidmc_unet *u, float decay);
+epidmc_status epidmc_unet_get_ema_params(const epidmc_unet *u, float *dev_params, void *stream);
+
 /* Denoise n <= bound images: noisy and thickness FP64 [n][h][w] (MeV per history and cm),
  * out FP64 [n][h][w] in the units of noisy. */
 epidmc_status epidmc_unet_forward(epidmc_unet *u, const double *noisy, const double *thickness, double *out,

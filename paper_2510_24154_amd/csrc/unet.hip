@@ -654,8 +654,10 @@ __global__ __launch_bounds__(WG) void k_head_reduce(const float *part, int nblk,
     else if (loss) loss[0] = sh[0] / (double)P;
 }
 
+// Adam on the FP32 master weights; when ema != NULL the exponential moving average of the
+// weights follows: ema <- d * ema + (1 - d) * theta (after the step)
 __global__ void k_adam(float *th, const float *g, float *m, float *v, long long n, float lr, float b1, float b2,
-                       float eps, float bc1, float bc2)
+                       float eps, float bc1, float bc2, float *ema, float d)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -664,7 +666,9 @@ __global__ void k_adam(float *th, const float *g, float *m, float *v, long long 
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    th[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    const float t = th[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    th[i] = t;
+    if (ema) ema[i] = fmaf(d, ema[i] - t, t);
 }
 
 __global__ void k_fill_f32(float *p, long long n, float v)
@@ -801,9 +805,10 @@ struct epidmc_unet {
     char *ws = nullptr;
     bool have_params = false;
     int t = 0;   // Adam steps taken
+    float ema_decay = 0.0f;   // 0: no moving average of the weights
     struct {
         Buf X, x0, tgt, scale, sumpart, headpart, wgs;
-        Buf theta, m, v, grad, wf, wb;
+        Buf theta, m, v, grad, wf, wb, ema;
         Buf ea[LEVELS], cat[LEVELS - 1], eb3, pl[LEVELS - 1], ul[LEVELS - 1], da[LEVELS - 1], db[LEVELS - 1];
         Buf gdb[LEVELS - 1], gda[LEVELS - 1], gcat[LEVELS - 1], gul[LEVELS - 1], geb[LEVELS], gea[LEVELS],
             gp[LEVELS - 1];
@@ -894,7 +899,7 @@ static size_t plan(epidmc_unet *u, int n, int h, int w)
     }
     take(y.wgs, wg * 4);
     const size_t np = u->nparam;
-    take(y.theta, np * 4); take(y.m, np * 4); take(y.v, np * 4); take(y.grad, np * 4);
+    take(y.theta, np * 4); take(y.m, np * 4); take(y.v, np * 4); take(y.grad, np * 4); take(y.ema, np * 4);
     take(y.wf, np * 2); take(y.wb, np * 2);
     for (int l = 0; l < LEVELS; ++l) {
         take(y.ea[l], P(l) * chan(l) * 2);
@@ -1269,6 +1274,7 @@ epidmc_status epidmc_unet_set_params(epidmc_unet *u, const float *dev_params, vo
     hipStream_t s = (hipStream_t)stream;
     const long long np = (long long)u->nparam;
     hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(np)), dim3(WG), 0, s, dev_params, at<float>(u, u->lay.theta), np);
+    hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(np)), dim3(WG), 0, s, dev_params, at<float>(u, u->lay.ema), np);
     hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(np)), dim3(WG), 0, s, at<float>(u, u->lay.m), np, 0.0f);
     hipLaunchKernelGGL(k_fill_f32, dim3(nblocks(np)), dim3(WG), 0, s, at<float>(u, u->lay.v), np, 0.0f);
     UCHK(hipGetLastError());
@@ -1285,6 +1291,25 @@ epidmc_status epidmc_unet_get_params(const epidmc_unet *u, float *dev_params, vo
     const long long np = (long long)u->nparam;
     hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(np)), dim3(WG), 0, (hipStream_t)stream,
                        (const float *)(u->ws + u->lay.theta.off), dev_params, np);
+    UCHK(hipGetLastError());
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_set_ema(epidmc_unet *u, float decay)
+{
+    if (!u) return EPIDMC_E_ARG;
+    UREQ(std::isfinite(decay) && decay >= 0.0f && decay < 1.0f, EPIDMC_E_ARG, "decay must be in [0, 1)");
+    u->ema_decay = decay;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_unet_get_ema_params(const epidmc_unet *u, float *dev_params, void *stream)
+{
+    if (!u || !dev_params) return EPIDMC_E_ARG;
+    UREQ(u->bound, EPIDMC_E_NOT_READY, "workspace not bound");
+    const long long np = (long long)u->nparam;
+    hipLaunchKernelGGL(k_copy_f32, dim3(nblocks(np)), dim3(WG), 0, (hipStream_t)stream,
+                       (const float *)(u->ws + u->lay.ema.off), dev_params, np);
     UCHK(hipGetLastError());
     return EPIDMC_OK;
 }
@@ -1346,7 +1371,8 @@ epidmc_status epidmc_unet_train_step(epidmc_unet *u, const double *noisy, const 
     const long long np = (long long)u->nparam;
     hipLaunchKernelGGL(k_adam, dim3(nblocks(np)), dim3(WG), 0, s, at<float>(u, u->lay.theta),
                        (const float *)at<float>(u, u->lay.grad), at<float>(u, u->lay.m), at<float>(u, u->lay.v), np, lr,
-                       (float)b1, (float)b2, 1e-8f, bc1, bc2);
+                       (float)b1, (float)b2, 1e-8f, bc1, bc2,
+                       u->ema_decay > 0.0f ? at<float>(u, u->lay.ema) : (float *)nullptr, u->ema_decay);
     UCHK(hipGetLastError());
     UCHK(weights_all(u, s));
     return EPIDMC_OK;

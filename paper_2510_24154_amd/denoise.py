@@ -15,7 +15,7 @@ DN_EXPORTS = [
     "epidmc_unet_create", "epidmc_unet_destroy", "epidmc_unet_last_error", "epidmc_unet_param_count",
     "epidmc_unet_layer", "epidmc_unet_layers", "epidmc_unet_workspace_size", "epidmc_unet_bind",
     "epidmc_unet_set_params", "epidmc_unet_get_params", "epidmc_unet_forward", "epidmc_unet_gradient",
-    "epidmc_unet_train_step",
+    "epidmc_unet_train_step", "epidmc_unet_set_ema", "epidmc_unet_get_ema_params",
 ]
 
 
@@ -43,6 +43,8 @@ def declare(L):
         "epidmc_unet_forward": [vp, vp, vp, vp, i32, vp],
         "epidmc_unet_gradient": [vp, vp, vp, vp, i32, vp, vp, vp],
         "epidmc_unet_train_step": [vp, vp, vp, vp, i32, f32, vp, vp],
+        "epidmc_unet_set_ema": [vp, f32],
+        "epidmc_unet_get_ema_params": [vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -231,6 +233,16 @@ class Unet:
         t = self.torch
         d = t.empty(self.nparam, dtype=t.float32, device=self.dev)
         self._c(self.L.epidmc_unet_get_params(self.h, _p(d), _stream(t)), "get_params")
+        return self.unflat(d.cpu().numpy())
+
+    def set_ema(self, decay):
+        """Keep an exponential moving average of the weights with this decay (0: off)."""
+        self._c(self.L.epidmc_unet_set_ema(self.h, float(decay)), "set_ema")
+
+    def get_ema_params(self):
+        t = self.torch
+        d = t.empty(self.nparam, dtype=t.float32, device=self.dev)
+        self._c(self.L.epidmc_unet_get_ema_params(self.h, _p(d), _stream(t)), "get_ema_params")
         return self.unflat(d.cpu().numpy())
 
     def forward(self, noisy, thickness, out=None):

@@ -385,3 +385,28 @@ def test_forward_replays_from_a_hip_graph(D):
         torch.cuda.synchronize()
         assert torch.equal(replayed, eager), rep
         assert float(replayed.abs().sum()) > 0
+
+
+def test_weight_moving_average_follows_the_steps(D):
+    """With decay d each Adam step sets ema <- d ema + (1 - d) theta; set_params resets it."""
+    import torch
+    P, noisy, th, target = net_case(seed=14)
+    net = D.Unet(0).bind(2, 16, 24)
+    net.set_params(P)
+    net.set_ema(0.9)
+    args = [torch.as_tensor(a).cuda() for a in (noisy, th, target)]
+    ema = {k: (W.astype(np.float64), b.astype(np.float64)) for k, (W, b) in P.items()}
+    for _ in range(3):
+        net.train_step(*args, lr=1e-3)
+        cur = net.get_params()
+        ema = {k: (0.9 * ema[k][0] + 0.1 * cur[k][0], 0.9 * ema[k][1] + 0.1 * cur[k][1]) for k in ema}
+    got = net.get_ema_params()
+    for k in ema:
+        np.testing.assert_allclose(got[k][0], ema[k][0], rtol=0, atol=1e-6, err_msg=k)
+        np.testing.assert_allclose(got[k][1], ema[k][1], rtol=0, atol=1e-6, err_msg=k)
+    assert not np.array_equal(got["e1b"][0], net.get_params()["e1b"][0])
+    net.set_params(P)                          # resets the average
+    np.testing.assert_array_equal(net.get_ema_params()["d0a"][0], P["d0a"][0])
+    from paper_2510_24154_amd import EpidmcError
+    with pytest.raises(EpidmcError, match="E_ARG"):
+        net.set_ema(1.0)
