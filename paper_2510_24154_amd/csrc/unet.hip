@@ -4,11 +4,13 @@
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16.  The reduction index runs
 // over groups of 8 input channels of one tap ("k-groups", kg = tap * c_in/8 + channel
-// group), so every MFMA operand is one 16-byte load of 8 consecutive NHWC channels:
-//   forward / backward-data   rows = pixels, columns = output channels; each lane loads its
-//                             A row (one pixel's 8 channels at the shifted position) and
-//                             B column (8 weights) straight from memory -- the 3x3 halo
-//                             re-reads hit L1/L2;
+// group), so every MFMA operand is one 16-byte word of 8 consecutive NHWC channels:
+//   forward / backward-data   rows = pixels, columns = output channels.  3x3 layers with
+//                             c_in a multiple of 32 (k_conv3_lds) stage a pixel tile with
+//                             its halo and the weight slab in LDS per 32-channel step and
+//                             read every operand from there; 1x1 layers and the 8-channel
+//                             input layer (k_conv) load each lane's operands straight from
+//                             memory;
 //   backward-weights          rows = output channels, columns = (tap, input channel), the
 //                             reduction runs over pixels, so both operands are staged
 //                             through LDS transposed; pixel chunks give FP32 partials that
