@@ -410,3 +410,31 @@ def test_weight_moving_average_follows_the_steps(D):
     from paper_2510_24154_amd import EpidmcError
     with pytest.raises(EpidmcError, match="E_ARG"):
         net.set_ema(1.0)
+
+
+def test_gradient_at_the_training_shape_matches_a_directional_difference(D):
+    """At the benchmark's training shape (8 crops of 256 x 256), the loss change along the
+    normalised gradient, by a central difference of two GPU forward passes, matches the
+    gradient's norm.  The step moves the loss by about 1%, far above the BF16 rounding of
+    the loss, so 10% agreement checks the backward pass at full size."""
+    import torch
+    rng = np.random.default_rng(21)
+    n, h, w = 8, 256, 256
+    P = synth.unet_params(U.layer_shapes(), seed=21, head_scale=0.05)
+    noisy = rng.gamma(2.0, 1e-5, (n, h, w))
+    th = rng.uniform(5, 30, (n, h, w))
+    target = noisy * rng.uniform(0.8, 1.2, (n, h, w))
+    net = D.Unet(0).bind(n, h, w)
+    net.set_params(P)
+    args = [torch.as_tensor(a).cuda() for a in (noisy, th, target)]
+    loss0, g = net.gradient(*args)
+    gn = np.sqrt(sum(float(np.sum(gw.astype(np.float64) ** 2) + np.sum(gb.astype(np.float64) ** 2))
+                     for gw, gb in g.values()))
+    eps = 0.01 * loss0 / gn                    # a step that changes the loss by about 1%
+    def moved(sign):
+        Q = {k: (W + sign * eps * g[k][0] / gn, b + sign * eps * g[k][1] / gn) for k, (W, b) in P.items()}
+        net.set_params(Q)
+        return net.gradient(*args)[0]
+    d = (moved(+1) - moved(-1)) / (2 * eps)
+    print("directional derivative", d, "gradient norm", gn, "loss", loss0)
+    assert d == pytest.approx(gn, rel=0.1)

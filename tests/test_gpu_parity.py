@@ -333,3 +333,19 @@ def test_segmented_field_beyond_2_32_histories(E):
         imgs.append(eng.image()[0].cpu().numpy())
     assert imgs[0].sum() > 0
     np.testing.assert_array_equal(imgs[0], imgs[1])
+
+
+def test_bench_configuration_energy_ledger(E):
+    """The benchmark's launch configuration: the full coupled workload, 1e8 histories as one
+    2^27-history chunk, 64 batches, with the per-history energy ledger on: every history
+    closes to 1e-9 and the image is finite."""
+    cfg = synth.coupled_hetero()
+    eng = E.Engine(0, seed=1).configure(cfg, batches=64, max_chunk=1 << 27, diag=True)
+    eng.bind()
+    eng.run(100_000_000)
+    c = eng.counters()
+    print("bench configuration: ledger", c["max_ledger_resid"], "woodcock/history", c["woodcock_steps"] / 1e8)
+    assert c["error_word"] == 0 and c["max_ledger_resid"] < 1e-9
+    assert c["e_deposited"] == pytest.approx(c["e_in"], rel=1e-12)
+    m, v = eng.image()
+    assert bool(np.isfinite(m.cpu().numpy()).all()) and float(m.sum()) > 0
