@@ -448,7 +448,10 @@ __global__ __launch_bounds__(WG) void k_source(Params P)
 // ---------------------------------------------------------------------------------
 // photons in the phantom: Woodcock tracking
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
+// Six waves per SIMD (the most the LDS staging allows: six workgroups per CU): the kernel
+// is VALU-bound on divergent code and its voxel gathers miss L2 about half the time, so the
+// extra wave hides latency.  It costs one spilled register.
+__global__ __launch_bounds__(WG, 6) void k_photon_phantom(Params P)
 {
     // dynamic LDS: per wave two staging buffers (electrons for the phantom queue, photons
     // for the EPID queue).  The packed tables (16 KB of mu/rho, 32 KB of process fractions)
@@ -465,10 +468,6 @@ __global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
     Part p;
     Local L;
     zero(L);
-    float imubar = 1.0f, mubar = 1.0f;
-    float4 mu = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // mu/rho of the four phantom slots at p.E
-    Node nd{0, 0.0f};
-    float e_cached = -1.0f;
     unsigned long long lane_iters = 0, wave_iters = 0;
     for (;;) {
         stage_flush_all(P, S, SBUF / 2);
@@ -488,19 +487,18 @@ __global__ __launch_bounds__(WG) void k_photon_phantom(Params P)
             leave = !in_phantom(P, p.x, p.y, p.z);   // a source photon whose ray misses the box
         }
         if (active && !leave) {
-            if (p.E != e_cached) {
-                e_cached = p.E;
-                nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
-                const float4 a = P.ph_mu4[nd.i], b = P.ph_mu4[nd.i + 1];
-                mu.x = fmaf(nd.f, b.x - a.x, a.x);
-                mu.y = fmaf(nd.f, b.y - a.y, a.y);
-                mu.z = fmaf(nd.f, b.z - a.z, a.z);
-                mu.w = fmaf(nd.f, b.w - a.w, a.w);
-                // the majorant: each slot's largest density times its mu/rho, so that it bounds
-                // rho mu/rho of every voxel at this energy exactly as interpolated here
-                mubar = fmaxf(fmaxf(P.rmaj[0] * mu.x, P.rmaj[1] * mu.y), fmaxf(P.rmaj[2] * mu.z, P.rmaj[3] * mu.w));
-                imubar = 1.0f / mubar;
-            }
+            // mu/rho of the four phantom slots at p.E.  Recomputed on every iteration: some lane
+            // of the wave takes a new energy on nearly every iteration, so a per-lane cache would
+            // save no wave instructions, and its registers are worth the sixth wave.
+            const Node nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
+            const float4 a = P.ph_mu4[nd.i], b = P.ph_mu4[nd.i + 1];
+            const float4 mu = make_float4(fmaf(nd.f, b.x - a.x, a.x), fmaf(nd.f, b.y - a.y, a.y),
+                                          fmaf(nd.f, b.z - a.z, a.z), fmaf(nd.f, b.w - a.w, a.w));
+            // the majorant: each slot's largest density times its mu/rho, so that it bounds
+            // rho mu/rho of every voxel at this energy exactly as interpolated here
+            const float mubar =
+                fmaxf(fmaxf(P.rmaj[0] * mu.x, P.rmaj[1] * mu.y), fmaxf(P.rmaj[2] * mu.z, P.rmaj[3] * mu.w));
+            const float imubar = 1.0f / mubar;
             // One Philox draw per lane and iteration, so that every lane of the wave spends its
             // random-number work together: a flight uses it for the distance, the real/virtual
             // test, the process and the first Klein-Nishina trial; a pending Compton sample
