@@ -108,8 +108,11 @@ struct epidmc_ctx {
     // profiling
     int prof = 0;
     hipEvent_t ev[2][NQ] = {};
-    // one stream per particle kind: the kinds of a pass run concurrently, so a pass lasts
-    // as long as its slowest kernel rather than the sum of them
+    // the kinds of a pass run concurrently, so a pass lasts as long as its slowest kernel
+    // rather than the sum of them: kinds 0..NQ-2 on streams of their own, the last kind on
+    // the run stream itself, so that the run takes NQ streams, as many as the hardware
+    // queues a process gets by default (a fifth stream would share a queue with another
+    // and serialise behind it)
     hipStream_t ks[NQ] = {};
     hipEvent_t go = nullptr, done[NQ] = {};
     double kernel_ms[NQ] = {0, 0, 0, 0};
@@ -804,7 +807,7 @@ static uint64_t batch_start(uint64_t first, uint64_t n, int B, uint64_t b)
 static epidmc_status kind_streams(epidmc_ctx *c)
 {
     if (c->go) return EPIDMC_OK;
-    for (int k = 0; k < NQ; ++k) {
+    for (int k = 0; k < NQ - 1; ++k) {
         HIPCHK(hipStreamCreateWithFlags(&c->ks[k], hipStreamNonBlocking));   // default priority
         HIPCHK(hipEventCreateWithFlags(&c->done[k], hipEventDisableTiming));
     }
@@ -870,25 +873,28 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
         HIPCHK(launch_zero(seg + 2 * SEG_SET, SEG_SET * 4, s));
         use(cur);
         // the pass's kernels start together once the counters are cleared, each on its
-        // kind's stream; the run stream waits for all of them before the next pass
+        // kind's stream (the last kind on the run stream); the run stream then waits for
+        // the others before the next pass
         HIPCHK(hipEventRecord(c->go, s));
         for (int k = 0; k < NQ; ++k) {
             if (!n[k]) continue;
             const uint64_t per_block = (uint64_t)WG * ITEMS_PER_LANE;
             const uint64_t want = (n[k] + per_block - 1) / per_block;
             const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * c->occ[k]));
-            hipStream_t ks = c->ks[k];
-            HIPCHK(hipStreamWaitEvent(ks, c->go, 0));
+            const bool own = k < NQ - 1;
+            hipStream_t ks = own ? c->ks[k] : s;
+            if (own) HIPCHK(hipStreamWaitEvent(ks, c->go, 0));
             if (c->prof) HIPCHK(hipEventRecord(c->ev[0][k], ks));
             HIPCHK(launch_transport(k, P, blocks, ks));
             if (c->prof) {
                 HIPCHK(hipEventRecord(c->ev[1][k], ks));
                 timed[k] = true;
             }
-            HIPCHK(hipEventRecord(c->done[k], ks));
-            HIPCHK(hipStreamWaitEvent(s, c->done[k], 0));
+            if (own) HIPCHK(hipEventRecord(c->done[k], ks));
             ++c->launches;
         }
+        for (int k = 0; k < NQ - 1; ++k)
+            if (n[k]) HIPCHK(hipStreamWaitEvent(s, c->done[k], 0));
         cur = 1 - cur;
     }
     if (c->tally_mode == 2) {
