@@ -25,7 +25,8 @@ hipError_t launch_image(const Params &P, double n, double nb, double *mean, doub
 hipError_t launch_sigma_bar(const Params &P, double n, double nb, double thr, double *out, hipStream_t s);
 hipError_t launch_diag_check(const Params &P, uint32_t nh, unsigned long long *maxbits, double *sums, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
-hipError_t launch_seg_total(const Params &P, const uint32_t *cnt, uint32_t *tot, hipStream_t s);
+hipError_t launch_pass_start(const Params &P, const uint32_t *cnt, uint32_t *tot, uint32_t *fills, uint32_t *heads,
+                             size_t words, hipStream_t s);
 hipError_t launch_radthick(const RadArgs &A, hipStream_t s);
 hipError_t launch_response(const RespArgs &A, hipStream_t s);
 hipError_t launch_dbg_philox(const Params &P, const uint32_t *ctr, uint32_t *out, unsigned long long n, hipStream_t s);
@@ -847,9 +848,11 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
     int cur = 0;
     bool timed[NQ] = {false, false, false, false};
     for (int pass = 0; pass < 100000; ++pass) {
-        HIPCHK(launch_seg_total(P, seg + cur * SEG_SET, cnt, s));
-        HIPCHK(hipMemcpyAsync(c->host, cnt, NQ * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(c->host + NQ, P.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        // the input set's totals and the error word in one readback; the kernel also clears
+        // the other set's fill counters and the consume heads for this pass (the previous
+        // pass, which used them, has ended: the run stream waited for it)
+        HIPCHK(launch_pass_start(P, seg + cur * SEG_SET, cnt, seg + (1 - cur) * SEG_SET, seg + 2 * SEG_SET, SEG_SET, s));
+        HIPCHK(hipMemcpyAsync(c->host, cnt, (NQ + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int k = 0; k < NQ; ++k)
             if (timed[k]) {
@@ -868,9 +871,6 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
             c->queue_peak = std::max<uint64_t>(c->queue_peak, n[k]);
         }
         if (!any) break;
-        // clear the other set's fill counters and all consume heads
-        HIPCHK(launch_zero(seg + (1 - cur) * SEG_SET, SEG_SET * 4, s));
-        HIPCHK(launch_zero(seg + 2 * SEG_SET, SEG_SET * 4, s));
         use(cur);
         // the pass's kernels start together once the counters are cleared, each on its
         // kind's stream (the last kind on the run stream); the run stream then waits for

@@ -1168,13 +1168,26 @@ __global__ void k_diag_check(Params P, uint32_t nh, unsigned long long *maxbits,
 // particles in each queue after a pass: the sum over its segments of min(fill, segcap);
 // one workgroup, wave k sums queue k (NSEG = 64 segments, one per lane)
 static_assert(NSEG == 64 && WG == 64 * NQ, "one lane per segment, one wave per queue");
-__global__ void k_seg_total(Params P, const uint32_t *cnt, uint32_t *tot)
+// Start of a queue pass: workgroup 0 adds up the input set's segment fills per kind
+// (clamped to the segment capacity) into tot[0..NQ-1] and copies the error word to tot[NQ],
+// so that the host reads both back at once; every workgroup also clears its share of the
+// other set's fill counters and of the consume heads (n16 16-byte words each), which the
+// pass's appends and claims start from.
+__global__ void k_pass_start(Params P, const uint32_t *cnt, uint32_t *tot, uint4 *fills, uint4 *heads, uint32_t n16)
 {
-    const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t v = min(cnt[((uint32_t)k * NSEG + lane) * CSTRIDE], P.segcap[k]);
+    if (blockIdx.x == 0) {
+        const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        uint32_t v = min(cnt[((uint32_t)k * NSEG + lane) * CSTRIDE], P.segcap[k]);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) tot[k] = v;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) tot[k] = v;
+        if (threadIdx.x == 0) tot[NQ] = *P.err;
+    }
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += gridDim.x * blockDim.x) {
+        fills[i] = z;
+        heads[i] = z;
+    }
 }
 
 __global__ void k_zero_u32(uint32_t *a, size_t n)
@@ -1494,9 +1507,12 @@ hipError_t launch_response(const RespArgs &A, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_seg_total(const Params &P, const uint32_t *cnt, uint32_t *tot, hipStream_t s)
+hipError_t launch_pass_start(const Params &P, const uint32_t *cnt, uint32_t *tot, uint32_t *fills, uint32_t *heads,
+                             size_t words, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_seg_total, dim3(1), dim3(WG), 0, s, P, cnt, tot);
+    if (words % 4 != 0 || cnt == nullptr || tot == nullptr || fills == nullptr || heads == nullptr) return hipErrorInvalidValue;
+    const uint32_t n16 = (uint32_t)(words / 4);
+    hipLaunchKernelGGL(k_pass_start, dim3(8), dim3(WG), 0, s, P, cnt, tot, (uint4 *)fills, (uint4 *)heads, n16);
     return hipGetLastError();
 }
 
