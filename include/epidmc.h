@@ -199,8 +199,8 @@ epidmc_status epidmc_set_tally(epidmc_ctx *c, epidmc_tally_mode mode, int batche
                                uint64_t max_chunk_histories);
 /* Diagnostics: when on, every history's energy ledger is kept on the device and checked. */
 epidmc_status epidmc_set_diagnostics(epidmc_ctx *c, int enable);
-/* Profiling: when on, every transport launch is bracketed by HIP events on the run stream
- * and the durations are summed into epidmc_counters.kernel_ms. */
+/* Profiling: when on, every transport launch is bracketed by HIP events on the stream it
+ * runs on and the durations are summed into epidmc_counters.kernel_ms. */
 epidmc_status epidmc_set_profiling(epidmc_ctx *c, int enable);
 
 /* ---- memory ------------------------------------------------------------------ */
@@ -214,7 +214,10 @@ epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev_ptr, size_t bytes, 
  * into the configured number of variance batches, and fold them into the tally.
  * Returns after the work has completed.  History ids are 64-bit: the random stream of
  * history h is keyed by the seed and h's high 32 bits, and counted by its low 32 bits, so
- * ids below 2^32 keep the plain seed key.  A segmented field's ids stay below its total. */
+ * ids below 2^32 keep the plain seed key.  A segmented field's ids stay below its total.
+ * Within a queue pass the four particle kinds run concurrently: three on streams the
+ * context creates (default priority) and the last on `stream`, which waits for the
+ * others before the next pass. */
 epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first_history, uint64_t n_histories, void *stream);
 /* Run chunks of `step_histories` from history `first_history` until the mean relative
  * standard deviation over pixels with D >= threshold_frac * max(D) is <= target, or
