@@ -601,15 +601,16 @@ __global__ __launch_bounds__(WG, 6) void k_photon_phantom(Params P)
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
 {
-    // dynamic LDS: the layer tables, then per wave one staging buffer for the electrons set
-    // in motion in the EPID
+    // dynamic LDS: per wave one staging buffer for the electrons set in motion in the EPID.
+    // The layer tables (48 KB for four layers) are read from global memory, where they stay
+    // in the caches: in LDS they made a workgroup too large to fit beside the phantom
+    // electron kernel, which runs in the same passes, and this kernel then ran on the few
+    // CUs that kernel left free.
     extern __shared__ __align__(16) float lds[];
     __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS];
-    const int ntab = P.nl * 3 * NB_PH;
-    const float *src = P.ph_tab + MAX_PMAT * 3 * NB_PH;
-    for (int i = threadIdx.x; i < ntab; i += WG) lds[i] = src[i];
+    const float *ltab = P.ph_tab + MAX_PMAT * 3 * NB_PH;
     Stages S;
-    stage_carve(S, (uint32_t *)(lds + ntab) + wave_id() * stage_words(SBUF), 1u << QEE, SBUF);
+    stage_carve(S, (uint32_t *)lds + wave_id() * stage_words(SBUF), 1u << QEE, SBUF);
     if (threadIdx.x <= MAX_LAYERS) s_zl[threadIdx.x] = P.zl[threadIdx.x];
     if (threadIdx.x < MAX_LAYERS) s_rho[threadIdx.x] = P.lrho[threadIdx.x];
     __syncthreads();
@@ -643,7 +644,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
         float u1 = r.x, u2 = r.y;
         if (!kn) {
             const int l = (int)((p.flags & F_LAYER_MASK) >> F_LAYER_SHIFT);
-            const float *tab = lds + l * 3 * NB_PH;
+            const float *tab = ltab + l * 3 * NB_PH;
             const Node nd = node_of(__logf(p.E), P.ph_lnE0, P.ph_idl, NB_PH);
             const float mu = s_rho[l] * lerp_tab(tab, nd);
             // distance to the slab planes and to the lateral faces
@@ -1412,7 +1413,7 @@ size_t lds_bytes(int kind, const Params &P)
 {
     switch (kind) {
     case QGP: return (size_t)(WG / 64) * 2 * stage_words(SBUF) * 4;
-    case QGE: return (size_t)P.nl * 3 * NB_PH * sizeof(float) + (size_t)(WG / 64) * stage_words(SBUF) * 4;
+    case QGE: return (size_t)(WG / 64) * stage_words(SBUF) * 4;
     case QEP: return (size_t)P.nmat_ph * 3 * NB_EL * sizeof(float) + (size_t)(WG / 64) * 4 * stage_words(SBUF_E) * 4;
     default: return (size_t)P.nl * 3 * NB_EL * sizeof(float) + (size_t)(WG / 64) * 2 * stage_words(SBUF_E) * 4;
     }
