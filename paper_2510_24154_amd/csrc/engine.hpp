@@ -20,8 +20,11 @@ constexpr int SBUF = 64;           // particles a wave stages in LDS per queue k
 constexpr int SBUF_E = 16;         // the same for the electron kernels, whose appends are rarer
 constexpr int NSEG = 64;           // segments per queue, each with its own fill counter and consume head
 constexpr int CSTRIDE = 32;        // u32 words from one segment counter to the next (one 128-byte line each)
-constexpr int ITEMS_PER_LANE = 8;  // a pass launches enough waves for about this many items per lane:
-                                   // a wave lives as long as its slowest particle, so thinner waves waste lanes
+constexpr int ITEMS_PER_LANE = 2;  // a pass launches enough waves for about this many items per lane:
+                                   // a wave lives as long as its slowest particle, so thinner waves waste
+                                   // lanes, while more items per lane lengthen a small pass, which lasts
+                                   // as long as one lane's chain of particles (of 8, 4, 2 and 1, 2 is the
+                                   // fastest on short runs and long ones)
 
 // queue kinds: photons / electrons (both signs) x phantom / EPID
 enum QKind { QGP = 0, QEP = 1, QGE = 2, QEE = 3, NQ = 4 };

@@ -481,10 +481,11 @@ static Layout make_layout(const epidmc_ctx *c)
     L.cap[QEP] = (uint32_t)(4 * H + 4096);
     L.cap[QGE] = (uint32_t)(2 * H + 4096);
     L.cap[QEE] = (uint32_t)(2 * H + 4096);
-    // A pass of n items runs on about n / (WG * ITEMS_PER_LANE) workgroups, so its waves use
-    // min(n / 512, NSEG) home segments.  Every segment therefore holds at least MIN_SEGCAP
-    // particles: with fewer than NSEG segments in use, a segment takes the appends of about 512
-    // items (a few thousand particles); with all in use, 1/NSEG of the queue's capacity.
+    // A pass of n items runs on about n / (WG * ITEMS_PER_LANE) workgroups, i.e. n / 128
+    // waves, so its waves use min(n / 128, NSEG) home segments.  Every segment therefore holds
+    // at least MIN_SEGCAP particles: with fewer than NSEG segments in use, a segment takes the
+    // appends of about 128 items (at most a few thousand particles); with all in use, 1/NSEG of
+    // the queue's capacity.
     constexpr uint32_t MIN_SEGCAP = 16384;
     for (int k = 0; k < NQ; ++k) {
         L.segcap[k] = std::max<uint32_t>((L.cap[k] + NSEG - 1) / NSEG, MIN_SEGCAP);
