@@ -1166,14 +1166,12 @@ __global__ void k_diag_check(Params P, uint32_t nh, unsigned long long *maxbits,
     unsafeAtomicAdd(&sums[1], led);
 }
 
-// particles in each queue after a pass: the sum over its segments of min(fill, segcap);
-// one workgroup, wave k sums queue k (NSEG = 64 segments, one per lane)
-static_assert(NSEG == 64 && WG == 64 * NQ, "one lane per segment, one wave per queue");
 // Start of a queue pass: workgroup 0 adds up the input set's segment fills per kind
-// (clamped to the segment capacity) into tot[0..NQ-1] and copies the error word to tot[NQ],
-// so that the host reads both back at once; every workgroup also clears its share of the
-// other set's fill counters and of the consume heads (n16 16-byte words each), which the
-// pass's appends and claims start from.
+// (clamped to the segment capacity; wave k sums queue k, one lane per segment) into
+// tot[0..NQ-1] and copies the error word to tot[NQ], so that the host reads both back at
+// once; every workgroup also clears its share of the other set's fill counters and of the
+// consume heads (n16 16-byte words each), which the pass's appends and claims start from.
+static_assert(NSEG == 64 && WG == 64 * NQ, "one lane per segment, one wave per queue");
 __global__ void k_pass_start(Params P, const uint32_t *cnt, uint32_t *tot, uint4 *fills, uint4 *heads, uint32_t n16)
 {
     if (blockIdx.x == 0) {
