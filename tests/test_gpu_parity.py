@@ -183,6 +183,28 @@ def test_fixed_point_bit_reproducible_across_launch_shapes(E):
     assert imgs[0][0].sum() > 0
 
 
+def test_fixed_point_same_on_a_side_stream_with_profiling(E):
+    """A pass runs three particle kinds on the engine's own streams and the fourth on the
+    caller's stream, which waits for the others before the next pass.  Issued on a
+    non-default stream, with profiling events around every launch, a run gives the same
+    fixed-point image as on the default stream, and every kind's launches are timed."""
+    import torch
+    cfg = synth.coupled_hetero_small()
+    m0, v0, _ = gpu_image(E, cfg, 400_000, seed=11, tally=1, max_chunk=1 << 16)
+    side = torch.cuda.Stream()   # default priority
+    with torch.cuda.stream(side):
+        eng = E.Engine(0, seed=11).configure(cfg, tally=1, batches=64, max_chunk=1 << 16)
+        eng.bind()
+        eng.set_profiling(True)
+        eng.run(400_000)
+        m, v = eng.image()
+    side.synchronize()
+    assert np.array_equal(m.cpu().numpy(), m0) and np.array_equal(v.cpu().numpy(), v0)
+    c = eng.counters()
+    assert all(n > 0 for n in c["kernel_launches"]), c["kernel_launches"]
+    assert all(ms > 0 for ms in c["kernel_ms"]), c["kernel_ms"]
+
+
 def test_tally_modes_agree(E):
     """Same seed, same trajectories: FP64 atomics, int64 fixed point and FP32 Kahan records
     give the same image up to their rounding (fixed point 2^-32 MeV per deposit, FP32)."""
