@@ -1,5 +1,5 @@
-"""CPU checks of bench.py's host logic: the equal-accuracy fit of the denoiser comparison and
-the refusal of more than one GPU."""
+"""CPU checks of bench.py's host logic: the equal-accuracy fit of the denoiser comparison, the
+reading of profiled HBM traffic, and the refusal of more than one GPU."""
 import os
 import subprocess
 import sys
@@ -32,3 +32,20 @@ def test_more_than_one_gpu_is_refused():
                        text=True, cwd=ROOT, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_profiled_traffic_needs_the_current_sources_and_workload(tmp_path, monkeypatch):
+    """The traffic figure comes from a profile summary only when the summary was taken on
+    the current kernel sources and the same workload; otherwise the JSON line carries null."""
+    import bench
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "k.md").write_text("# summary\n\n    source_sha: abc123\n    workload: coupled\n"
+                               "    traffic_bytes_per_unit[k_photon_phantom]: 80.5\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "abc123")
+    assert bench.profiled_traffic("k_photon_phantom", "coupled") == (80.5, "k.md")
+    assert bench.profiled_traffic("k_photon_phantom", "imrt40") == (None, None)
+    assert bench.profiled_traffic("k_electron<phantom>", "coupled") == (None, None)
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "def456")
+    assert bench.profiled_traffic("k_photon_phantom", "coupled") == (None, None)
