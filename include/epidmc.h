@@ -259,6 +259,17 @@ epidmc_status epidmc_dose_response(epidmc_ctx *c, const double *dev_image, const
                                    const double *t_nodes, int nt, const double *s_nodes, int ns,
                                    const double *k, double *dev_out, void *stream);
 
+/* Resample a k(t,s) table onto other nodes (Sec. 3.1: Table 1 resampled onto the finer
+ * 64 x 64 table of a large field, up to 64 nodes per axis): k_out[j*mt + i] = k(t_out[i],
+ * s_out[j]), with k bilinear on t_nodes[nt] x s_nodes[ns] (k[j*nt + i] at (t_i, s_j)) and t, s
+ * clamped to the table's edges, exactly as epidmc_dose_response evaluates it.  When the new
+ * nodes include the old ones, the new table interpolates to the same function.  Host
+ * arrays; host computation, no device work.  EPIDMC_E_ARG for null pointers, EPIDMC_E_RANGE
+ * for sizes outside 1..64, unordered nodes or non-finite values. */
+epidmc_status epidmc_resample_response_table(const double *t_nodes, int nt, const double *s_nodes, int ns,
+                                             const double *k, const double *t_out, int mt, const double *s_out,
+                                             int ms, double *k_out);
+
 /* ---- diagnostics of the device building blocks (test entry points) ----------- */
 /* Philox4x32-10 on the device: out[4*i..4*i+3] = philox(ctr[4*i..], key).  Device pointers. */
 epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *dev_ctr, uint32_t *dev_out, uint64_t n,
@@ -266,11 +277,19 @@ epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *dev_ctr, uint32
 /* Device samplers: kind 0 Klein-Nishina eps = E'/E at energy p0; kind 1 Moller energy
  * transfer at kinetic energy p0; kind 2 bremsstrahlung photon energy at p0; kind 3
  * multiple-scattering polar angle for kinetic energy p0 over p1 g/cm^2 of material p2;
- * kind 4 the source: 8 floats (x y z u v w E type) per history starting at history
- * p0; kind 5 the azimuth uniform that accompanies a kind-0 sample (uniform on (0, 1)).
- * n samples into dev_out. */
+ * kind 4 the source: 8 floats (x y z u v w E type) per history for histories
+ * [p0, p0 + n), p0 an integer below 2^53 and the range within one 2^32 block, drawn by the
+ * source kernel's own sampling function with its key; kind 5 the azimuth uniform that
+ * accompanies a kind-0 sample (uniform on (0, 1)).  n samples into dev_out. */
 epidmc_status epidmc_debug_sample(epidmc_ctx *c, int kind, double p0, double p1, double p2, float *dev_out,
                                   uint64_t n, void *stream);
+/* Deposit records of the last chunk transported in the Kahan tally mode, the tally's raw
+ * input (a test entry point: re-binned on the host they must give the tally): up to cap
+ * records copied on `stream` to dev_pix (image element = variance-batch slot * npx_u * npx_v
+ * + pixel index) and dev_e (MeV, FP32); *n receives the chunk's record count, which may
+ * exceed cap.  Device pointers.  EPIDMC_E_NOT_READY outside the Kahan mode or before a run. */
+epidmc_status epidmc_debug_records(epidmc_ctx *c, uint32_t *dev_pix, float *dev_e, uint64_t cap, uint64_t *n,
+                                   void *stream);
 /* The device cross-section tables evaluated at energies: kind 0 photon mu/rho of
  * material slot `index` (phantom slots 0..3, EPID layers 4..), kind 1 electron range,
  * kind 2 electron hard cross section (phantom slots 0..3, EPID layers 4..). */

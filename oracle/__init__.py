@@ -55,7 +55,29 @@ class Config(ct.Structure):
         ("seg_hist", ct.POINTER(ct.c_uint64)),
         ("n_phsp", ct.c_uint64), ("phsp", ct.POINTER(ct.c_double)),
         ("seed", ct.c_uint64),
+        ("step_floor", ct.c_double),
     ]
+
+
+# event kinds of the trace (epid_oracle.h, orc_event)
+EV_DEPOSIT, EV_ESTEP, EV_COMPTON, EV_PHOTO, EV_PAIR, EV_ANNIH, EV_MOLLER, EV_BREMS, EV_NULL = range(9)
+
+
+class Event(ct.Structure):
+    _fields_ = [("hist", ct.c_uint64), ("kind", ct.c_int32), ("region", ct.c_int32), ("layer", ct.c_int32),
+                ("pixel", ct.c_int32), ("pos", ct.c_double * 3), ("E0", ct.c_double), ("E1", ct.c_double),
+                ("d0", ct.c_double * 3), ("d1", ct.c_double * 3), ("Ec", ct.c_double * 2),
+                ("dc", (ct.c_double * 3) * 2), ("aux", ct.c_double * 2)]
+
+
+EVENT_DTYPE = np.dtype([("hist", np.uint64), ("kind", np.int32), ("region", np.int32), ("layer", np.int32),
+                        ("pixel", np.int32), ("pos", np.float64, 3), ("E0", np.float64), ("E1", np.float64),
+                        ("d0", np.float64, 3), ("d1", np.float64, 3), ("Ec", np.float64, 2),
+                        ("dc", np.float64, (2, 3)), ("aux", np.float64, 2)])
+assert EVENT_DTYPE.itemsize == ct.sizeof(Event)
+# floor on boundary-limited electron steps, as a fraction of the cell's smallest side: 0 in the
+# reading (a step never crosses a face); a test sets another value to measure what a floor does
+STEP_FLOOR = 0.0
 
 
 class Counters(ct.Structure):
@@ -72,49 +94,79 @@ class Counters(ct.Structure):
 
 
 _lib = None
+_override = None
 _lock = threading.Lock()
+
+
+class using:
+    """Context manager: route every call of this module through the oracle library at
+    `path` (a test build of the oracle's source) instead of the default one."""
+
+    def __init__(self, path: str):
+        self.L = _declare(ct.CDLL(path))
+
+    def __enter__(self):
+        global _override
+        self.prev, _override = _override, self.L
+        return self.L
+
+    def __exit__(self, *exc):
+        global _override
+        _override = self.prev
+        return False
 
 
 def lib():
     global _lib
+    if _override is not None:
+        return _override
     with _lock:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 build()
-            L = ct.CDLL(LIB_PATH)
-            d, p = ct.c_double, ct.c_void_p
-            L.orc_run.argtypes = [ct.POINTER(Config), ct.c_uint64, ct.c_uint64, p, p, ct.POINTER(Counters)]
-            L.orc_run.restype = ct.c_int
-            L.orc_map_hu.argtypes = [p, ct.c_uint64, ct.c_int, p, p, ct.c_int, p, p, p, p]
-            L.orc_map_hu.restype = ct.c_int
-            for name, args in {
-                "orc_sigma_kn": [d], "orc_kn_sample": [d, d], "orc_kn_cdf": [d, d],
-                "orc_x0": [ct.POINTER(Material)], "orc_highland": [d, d, d],
-                "orc_lcol": [ct.POINTER(Material), d, ct.c_int, d],
-                "orc_lres": [ct.POINTER(Material), d, d, d],
-                "orc_sigma_moller": [ct.POINTER(Material), d, d],
-                "orc_sigma_brems": [ct.POINTER(Material), d, d],
-                "orc_moller_sample": [d, d, d],
-                "orc_range_diff": [ct.POINTER(Material), d, d, d, d],
-                "orc_range_inverse": [ct.POINTER(Material), d, d, d, d],
-            }.items():
-                f = getattr(L, name)
-                f.argtypes = args
-                f.restype = d
-            L.orc_source.argtypes = [ct.POINTER(Config), ct.c_uint64, p]
-            L.orc_source.restype = ct.c_int
-            L.orc_photon_mu.argtypes = [ct.POINTER(Material), d, p]
-            L.orc_photon_mu.restype = None
-            L.orc_philox4x32_10.argtypes = [p, p, p]
-            L.orc_philox4x32_10.restype = None
-            L.orc_radiological_thickness.argtypes = [ct.POINTER(Config), p]
-            L.orc_radiological_thickness.restype = ct.c_int
-            L.orc_equivalent_square.argtypes = [ct.POINTER(Config)]
-            L.orc_equivalent_square.restype = d
-            L.orc_response_factor.argtypes = [p, ct.c_int, p, ct.c_int, p, d, d]
-            L.orc_response_factor.restype = d
-            _lib = L
+            _lib = _declare(ct.CDLL(LIB_PATH))
     return _lib
+
+
+def _declare(L):
+    d, p = ct.c_double, ct.c_void_p
+    L.orc_run.argtypes = [ct.POINTER(Config), ct.c_uint64, ct.c_uint64, p, p, ct.POINTER(Counters)]
+    L.orc_run.restype = ct.c_int
+    L.orc_run_traced.argtypes = [ct.POINTER(Config), ct.c_uint64, ct.c_uint64, p, p, ct.POINTER(Counters),
+                                 p, ct.c_uint64, ct.POINTER(ct.c_uint64)]
+    L.orc_run_traced.restype = ct.c_int
+    L.orc_map_hu.argtypes = [p, ct.c_uint64, ct.c_int, p, p, ct.c_int, p, p, p, p]
+    L.orc_map_hu.restype = ct.c_int
+    for name, args in {
+        "orc_sigma_kn": [d], "orc_kn_sample": [d, d], "orc_kn_cdf": [d, d],
+        "orc_x0": [ct.POINTER(Material)], "orc_highland": [d, d, d],
+        "orc_lcol": [ct.POINTER(Material), d, ct.c_int, d],
+        "orc_lres": [ct.POINTER(Material), d, d, d],
+        "orc_sigma_moller": [ct.POINTER(Material), d, d],
+        "orc_sigma_brems": [ct.POINTER(Material), d, d],
+        "orc_moller_sample": [d, d, d],
+        "orc_brems_sample": [d, d, d],
+        "orc_srad": [ct.POINTER(Material), d],
+        "orc_sigma_hard_max": [ct.POINTER(Material), d, d, d],
+        "orc_range_diff": [ct.POINTER(Material), d, d, d, d],
+        "orc_range_inverse": [ct.POINTER(Material), d, d, d, d],
+    }.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = d
+    L.orc_source.argtypes = [ct.POINTER(Config), ct.c_uint64, p]
+    L.orc_source.restype = ct.c_int
+    L.orc_photon_mu.argtypes = [ct.POINTER(Material), d, p]
+    L.orc_photon_mu.restype = None
+    L.orc_philox4x32_10.argtypes = [p, p, p]
+    L.orc_philox4x32_10.restype = None
+    L.orc_radiological_thickness.argtypes = [ct.POINTER(Config), p]
+    L.orc_radiological_thickness.restype = ct.c_int
+    L.orc_equivalent_square.argtypes = [ct.POINTER(Config)]
+    L.orc_equivalent_square.restype = d
+    L.orc_response_factor.argtypes = [p, ct.c_int, p, ct.c_int, p, d, d]
+    L.orc_response_factor.restype = d
+    return L
 
 
 def material(m: dict) -> Material:
@@ -194,6 +246,7 @@ class Prepared:
             self.phsp = np.ascontiguousarray(phsp, dtype=np.float64).reshape(-1, 8)
             c.n_phsp, c.phsp = self.phsp.shape[0], _dptr(self.phsp)
         c.seed = int(seed)
+        c.step_floor = float(ph.get("step_floor", STEP_FLOOR))
         self.c = c
         self.npix = E["npx_u"] * E["npx_v"]
         self.shape = (E["npx_v"], E["npx_u"])
@@ -242,6 +295,26 @@ def run(cfg: dict, n: int, seed: int = 1001, first: int = 0, threads: int = 1, p
     mean = s / n
     var = (s2 / n - mean * mean) / max(1, n - 1)
     return mean.reshape(P.shape), np.maximum(var, 0).reshape(P.shape), s, s2, cnt
+
+
+def run_traced(cfg: dict, n: int, seed: int = 1001, first: int = 0, cap: int = 1 << 20, phsp=None):
+    """Single-threaded run of histories [first, first+n) that also returns every event in
+    order as a structured array (EVENT_DTYPE); raises if more than `cap` events happen.
+
+    Returns (mean, var_of_mean, sum, sum2, counters-dict, events)."""
+    P = Prepared(cfg, seed, phsp)
+    ev = np.zeros(cap, dtype=EVENT_DTYPE)
+    s, s2, c = np.zeros(P.npix), np.zeros(P.npix), Counters()
+    nev = ct.c_uint64(0)
+    rc = lib().orc_run_traced(ct.byref(P.c), first, n, s.ctypes.data, s2.ctypes.data, ct.byref(c),
+                              ev.ctypes.data, cap, ct.byref(nev))
+    if rc != 0:
+        raise RuntimeError(f"orc_run_traced failed: {rc}")
+    if nev.value > cap:
+        raise RuntimeError(f"{nev.value} events exceed the trace capacity {cap}")
+    mean = s / n
+    var = (s2 / n - mean * mean) / max(1, n - 1)
+    return mean.reshape(P.shape), np.maximum(var, 0).reshape(P.shape), s, s2, c.as_dict(), ev[:nev.value]
 
 
 def radiological_thickness(cfg: dict) -> np.ndarray:

@@ -35,8 +35,6 @@
 #define WCUT     0.200         /* Moller hard-collision threshold (MeV) */
 #define KCUT     0.010         /* bremsstrahlung hard-photon threshold (MeV) */
 #define NUDGE    1.0e-5        /* cm pushed past a geometric boundary by a boundary-limited step */
-#define SKIN     0.05          /* a boundary-limited step is at least this fraction of the cell's
-                                  smallest dimension (no runs of vanishing steps along a face) */
 #define DE_FRAC  0.9           /* a step may take the energy down to DE_FRAC * T0 at most */
 #define MAX_E_STEPS 1000000
 
@@ -228,15 +226,16 @@ double orc_lcol(const orc_material *m, double T, int restricted, double wcut)
     return 2.0 * PI * RE_CM * RE_CM * MEC2 * mat_ne(m) / b2 * br;
 }
 
-static double srad(const orc_material *m, double T)
+double orc_srad(const orc_material *m, double T)
 {
+    /* radiative stopping power by the textbook ratio S_rad / S_col = Z_eff T / BREM_K */
     return orc_lcol(m, T, 0, 0.0) * mat_zeff(m) * T / BREM_K;
 }
 
 double orc_lres(const orc_material *m, double T, double wcut, double kcut)
 {
     /* restricted collision loss + soft (k < kcut) part of the 1/k bremsstrahlung spectrum */
-    return orc_lcol(m, T, 1, wcut) + srad(m, T) * kcut / T;
+    return orc_lcol(m, T, 1, wcut) + orc_srad(m, T) * kcut / T;
 }
 
 double orc_sigma_moller(const orc_material *m, double T, double wcut)
@@ -253,7 +252,23 @@ double orc_sigma_moller(const orc_material *m, double T, double wcut)
 double orc_sigma_brems(const orc_material *m, double T, double kcut)
 {
     if (T <= kcut) return 0.0;
-    return srad(m, T) / T * log(T / kcut);
+    return orc_srad(m, T) / T * log(T / kcut);
+}
+
+double orc_brems_sample(double T, double kcut, double xi)
+{
+    /* the 1/k spectrum on [kcut, T]: its CDF ln(k/kcut)/ln(T/kcut) inverted */
+    return kcut * exp(xi * log(T / kcut));
+}
+
+double orc_sigma_hard_max(const orc_material *m, double T0, double wcut, double kcut)
+{
+    /* the largest hard cross section over the energies a step from T0 can reach, [0.9 T0, T0]:
+     * Sigma_Moller + Sigma_brems rises with T on the electron energies in use (a pinned
+     * property), so the larger of the two end values bounds it */
+    double a = orc_sigma_moller(m, T0, wcut) + orc_sigma_brems(m, T0, kcut);
+    double b = orc_sigma_moller(m, DE_FRAC * T0, wcut) + orc_sigma_brems(m, DE_FRAC * T0, kcut);
+    return a > b ? a : b;
 }
 
 double orc_moller_sample(double T, double wcut, double xi)
@@ -476,7 +491,29 @@ typedef struct {
     double     dep, esc, rest;  /* ledger of this history */
     orc_counters *cnt;
     int        err;
+    uint64_t   hist;           /* history being transported */
+    orc_event *ev;             /* optional event trace */
+    uint64_t   ev_cap, ev_n;
 } ctx_t;
+
+/* the next trace record (zeroed), or NULL when tracing is off or the buffer is full */
+static orc_event *ev_new(ctx_t *c, int kind, const double p[3])
+{
+    if (!c->ev) return NULL;
+    uint64_t i = c->ev_n++;
+    if (i >= c->ev_cap) return NULL;
+    orc_event *e = &c->ev[i];
+    memset(e, 0, sizeof *e);
+    e->hist = c->hist;
+    e->kind = kind;
+    e->region = -1;
+    e->layer = -1;
+    e->pixel = -1;
+    for (int a = 0; a < 3; ++a) e->pos[a] = p[a];
+    return e;
+}
+
+static void vcopy(double d[3], const double s[3]) { d[0] = s[0]; d[1] = s[1]; d[2] = s[2]; }
 
 static void push(ctx_t *c, const double p[3], const double d[3], double E, int type, int region, int unscat)
 {
@@ -490,6 +527,8 @@ static void push(ctx_t *c, const double p[3], const double d[3], double E, int t
 static void deposit(ctx_t *c, int region, int layer, const double p[3], double E)
 {
     const orc_config *cf = c->g->c;
+    orc_event *ev = ev_new(c, ORC_EV_DEPOSIT, p);
+    if (ev) { ev->region = (region == R_PHANTOM || region == R_EPID) ? region : -1; ev->layer = layer; ev->E0 = E; }
     c->dep += E;
     if (region == R_PHANTOM) { c->cnt->e_dep_phantom += E; return; }
     if (region != R_EPID) { c->cnt->e_dep_other += E; return; }
@@ -498,6 +537,7 @@ static void deposit(ctx_t *c, int region, int layer, const double p[3], double E
     double fu = floor((p[0] + c->g->hx) / cf->pitch_u), fv = floor((p[1] + c->g->hy) / cf->pitch_v);
     if (!(fu >= 0 && fu < cf->npx_u && fv >= 0 && fv < cf->npx_v)) return;
     int pix = (int)fv * cf->npx_u + (int)fu;
+    if (ev) ev->pixel = pix;
     if (c->hacc[pix] == 0.0) c->touched[c->ntouched++] = pix;
     c->hacc[pix] += E;
     c->cnt->n_tally_deposits++;
@@ -514,6 +554,23 @@ static void deposit_at(ctx_t *c, int r, const double p[3], double E)
 
 static void escape(ctx_t *c, double E) { c->esc += E; c->cnt->e_escaped += E; }
 
+static void spawn(ctx_t *c, const double p[3], const double d[3], double E, int type, int r);
+
+/* a positron at rest at p (region r) annihilates into two photons of m c^2, back to back
+ * along an isotropic direction (reading R4) */
+static void annihilate(ctx_t *c, const double p[3], int r)
+{
+    double da[3], db[3];
+    isotropic(&c->rng, da);
+    db[0] = -da[0]; db[1] = -da[1]; db[2] = -da[2];
+    c->cnt->n_annih++;
+    c->rest -= 2.0 * MEC2;
+    orc_event *ev = ev_new(c, ORC_EV_ANNIH, p);
+    if (ev) { ev->Ec[0] = MEC2; ev->Ec[1] = MEC2; vcopy(ev->dc[0], da); vcopy(ev->dc[1], db); }
+    spawn(c, p, da, MEC2, P_PHOTON, r);
+    spawn(c, p, db, MEC2, P_PHOTON, r);
+}
+
 /* a newly created particle of kinetic energy E at p in region r (the parent's region) */
 static void spawn(ctx_t *c, const double p[3], const double d[3], double E, int type, int r)
 {
@@ -523,15 +580,7 @@ static void spawn(ctx_t *c, const double p[3], const double d[3], double E, int 
     } else {
         if (!cf->coupled || E < cf->ecut) {
             deposit_at(c, r, p, E);
-            if (type == P_POSITRON) {            /* annihilation at rest, two back-to-back photons */
-                double da[3], db[3];
-                isotropic(&c->rng, da);
-                db[0] = -da[0]; db[1] = -da[1]; db[2] = -da[2];
-                c->cnt->n_annih++;
-                c->rest -= 2.0 * MEC2;
-                spawn(c, p, da, MEC2, P_PHOTON, r);
-                spawn(c, p, db, MEC2, P_PHOTON, r);
-            }
+            if (type == P_POSITRON) annihilate(c, p, r);
             return;
         }
     }
@@ -585,11 +634,15 @@ static void photon_interact(ctx_t *c, part_t *ph, int m, int *alive)
         if (n > 0) { pe[0] /= n; pe[1] /= n; pe[2] /= n; } else { pe[0] = d0[0]; pe[1] = d0[1]; pe[2] = d0[2]; }
         ph->E = Ep;
         if (first) { c->cnt->n_first_collision++; c->cnt->e_first_collision += T; }
+        orc_event *ev = ev_new(c, ORC_EV_COMPTON, ph->p);
+        if (ev) { ev->E0 = E; ev->E1 = Ep; vcopy(ev->d0, d0); vcopy(ev->d1, ph->d); ev->Ec[0] = T; vcopy(ev->dc[0], pe); }
         spawn(c, ph->p, pe, T, P_ELECTRON, ph->region);
         if (Ep < cf->pcut) { deposit_at(c, ph->region, ph->p, Ep); *alive = 0; }
     } else if (x < muc + mup) {
         c->cnt->n_photo++;
         if (first) { c->cnt->n_first_collision++; c->cnt->e_first_collision += ph->E; }
+        orc_event *ev = ev_new(c, ORC_EV_PHOTO, ph->p);
+        if (ev) { ev->E0 = ph->E; vcopy(ev->d0, ph->d); ev->Ec[0] = ph->E; vcopy(ev->dc[0], ph->d); }
         spawn(c, ph->p, ph->d, ph->E, P_ELECTRON, ph->region);
         *alive = 0;
     } else {
@@ -598,6 +651,11 @@ static void photon_interact(ctx_t *c, part_t *ph, int m, int *alive)
         double tm = orng_u(&c->rng) * T, tp = T - tm;
         c->rest += 2.0 * MEC2;
         if (first) { c->cnt->n_first_collision++; c->cnt->e_first_collision += T; }
+        orc_event *ev = ev_new(c, ORC_EV_PAIR, ph->p);
+        if (ev) {
+            ev->E0 = ph->E; vcopy(ev->d0, ph->d);
+            ev->Ec[0] = tm; vcopy(ev->dc[0], ph->d); ev->Ec[1] = tp; vcopy(ev->dc[1], ph->d);
+        }
         spawn(c, ph->p, ph->d, tm, P_ELECTRON, ph->region);
         spawn(c, ph->p, ph->d, tp, P_POSITRON, ph->region);
         *alive = 0;
@@ -698,13 +756,13 @@ static double cell_distance(const geo_t *g, int region, const double p[3], const
         int idx[3]; voxel_of(g, p, idx);
         long v = ((long)idx[2] * cf->ny + idx[1]) * cf->nx + idx[0];
         *m_out = cf->vox_mat[v]; *rho_out = cf->vox_rho[v]; *layer_out = -1;
-        *smin = SKIN * fmin(cf->spacing[0], fmin(cf->spacing[1], cf->spacing[2]));
+        *smin = cf->step_floor * fmin(cf->spacing[0], fmin(cf->spacing[1], cf->spacing[2]));
         for (int a = 0; a < 3; ++a) { lo[a] = g->bmin[a] + idx[a] * cf->spacing[a]; hi[a] = lo[a] + cf->spacing[a]; }
     } else {
         int l = epid_layer_of(g, p);
         if (l < 0) l = (p[2] < g->zl[0]) ? 0 : cf->n_layers - 1;   /* on the entry plane */
         *layer_out = l; *m_out = cf->layer_mat[l]; *rho_out = cf->layer_rho[l];
-        *smin = SKIN * cf->layer_t[l];
+        *smin = cf->step_floor * cf->layer_t[l];
         lo[0] = -g->hx; hi[0] = g->hx; lo[1] = -g->hy; hi[1] = g->hy; lo[2] = g->zl[l]; hi[2] = g->zl[l + 1];
     }
     double t = INFINITY;
@@ -731,25 +789,39 @@ static void transport_electron(ctx_t *c, part_t e)
             c->cnt->e_track += sg;
             for (int a = 0; a < 3; ++a) e.p[a] += sg * e.d[a];
         } else {
-            double sh = (cf->proc_mask & 8) ? 0.0 : orc_sigma_moller(mat, T, WCUT) + orc_sigma_brems(mat, T, KCUT);
+            /* the distance to a hard event is drawn against the largest hard cross section
+             * the step can meet (its energy falls by at most 10%); at the end of such a step
+             * the event is real with probability Sigma_hard(T1) / that maximum */
+            double smax = (cf->proc_mask & 8) ? 0.0 : orc_sigma_hard_max(mat, T, WCUT, KCUT);
             double xi1 = orng_u(&c->rng), xi2 = orng_u(&c->rng), xi3 = orng_u(&c->rng), xi4 = orng_u(&c->rng);
-            double s_hard = sh > 0 ? -log(xi1) / (rho * sh) : INFINITY;
+            double s_hard = smax > 0 ? -log(xi1) / (rho * smax) : INFINITY;
             double s_de = orc_range_diff(mat, DE_FRAC * T, T, WCUT, KCUT) / rho;
             double s_pix = (e.region == R_EPID && layer == cf->scoring_layer) ? 0.5 * fmin(cf->pitch_u, cf->pitch_v) : INFINITY;
             double s = fmin(fmin(s_hard, s_de), fmin(sg, s_pix));
             int hard = s_hard <= fmin(s_de, fmin(sg, s_pix));
             double T1 = (s == s_de) ? DE_FRAC * T : orc_range_inverse(mat, T, rho * s, WCUT, KCUT);
-            double h[3];
+            double h[3], p0[3], d0[3];
+            vcopy(p0, e.p); vcopy(d0, e.d);
             c->cnt->e_track += s;
             for (int a = 0; a < 3; ++a) h[a] = e.p[a] + xi2 * s * e.d[a];
-            deposit(c, e.region, layer, h, T - T1);
-                    double th = (cf->proc_mask & 16) ? 0.0 : orc_highland(T, rho * s, g->x0[m]) * sqrt(-2.0 * log(xi3));
+            /* the continuous loss is left at the hinge point, in the cell that holds it */
+            deposit_at(c, e.region, h, T - T1);
+            double th = (cf->proc_mask & 16) ? 0.0 : orc_highland(T, rho * s, g->x0[m]) * sqrt(-2.0 * log(xi3));
             rotate(e.d, cos(th), sin(th), 2.0 * PI * xi4);
             for (int a = 0; a < 3; ++a) e.p[a] = h[a] + (1.0 - xi2) * s * e.d[a];
+            orc_event *ev = ev_new(c, ORC_EV_ESTEP, p0);
+            if (ev) {
+                ev->region = e.region; ev->layer = layer; ev->E0 = T; ev->E1 = T1;
+                vcopy(ev->d0, d0); vcopy(ev->d1, e.d); vcopy(ev->dc[0], h);
+                ev->aux[0] = s; ev->aux[1] = rho * s; ev->Ec[0] = g->x0[m];
+            }
             T = T1;
             if (hard) {
                 double sm = orc_sigma_moller(mat, T, WCUT), sb = orc_sigma_brems(mat, T, KCUT);
-                if (orng_u(&c->rng) * (sm + sb) < sm) {
+                double u = orng_u(&c->rng) * smax;
+                double dd0[3];
+                vcopy(dd0, e.d);
+                if (u < sm) {
                     c->cnt->n_moller++;
                     double W = orc_moller_sample(T, WCUT, orng_u(&c->rng));
                     double Tp = T - W;
@@ -759,28 +831,27 @@ static void transport_electron(ctx_t *c, part_t e)
                     double dd[3] = { e.d[0], e.d[1], e.d[2] };
                     rotate(dd, fmin(cd, 1.0), sqrt(fmax(0.0, 1.0 - cd * cd)), phi);
                     rotate(e.d, fmin(cp, 1.0), sqrt(fmax(0.0, 1.0 - cp * cp)), phi + PI);
+                    orc_event *em = ev_new(c, ORC_EV_MOLLER, e.p);
+                    if (em) { em->E0 = T; em->E1 = Tp; vcopy(em->d0, dd0); vcopy(em->d1, e.d); em->Ec[0] = W; vcopy(em->dc[0], dd); }
                     T = Tp;
                     spawn(c, e.p, dd, W, P_ELECTRON, e.region);
-                } else {
+                } else if (u < sm + sb) {
                     c->cnt->n_brems++;
-                    double k = KCUT * pow(T / KCUT, orng_u(&c->rng));
+                    double k = orc_brems_sample(T, KCUT, orng_u(&c->rng));
+                    orc_event *eb = ev_new(c, ORC_EV_BREMS, e.p);
+                    if (eb) { eb->E0 = T; eb->E1 = T - k; vcopy(eb->d0, dd0); vcopy(eb->d1, e.d); eb->Ec[0] = k; vcopy(eb->dc[0], e.d); }
                     T -= k;
                     spawn(c, e.p, e.d, k, P_PHOTON, e.region);
+                } else {
+                    orc_event *en = ev_new(c, ORC_EV_NULL, e.p);
+                    if (en) { en->E0 = T; vcopy(en->d0, e.d); }
                 }
             }
         }
         if (T < cf->ecut) {
             /* below the cut-off: deposit at the end point and, for a positron, annihilate there */
             deposit_at(c, e.region, e.p, T);
-            if (e.type == P_POSITRON) {
-                double da[3], db[3];
-                isotropic(&c->rng, da);
-                db[0] = -da[0]; db[1] = -da[1]; db[2] = -da[2];
-                c->cnt->n_annih++;
-                c->rest -= 2.0 * MEC2;
-                spawn(c, e.p, da, MEC2, P_PHOTON, e.region);
-                spawn(c, e.p, db, MEC2, P_PHOTON, e.region);
-            }
+            if (e.type == P_POSITRON) annihilate(c, e.p, e.region);
             return;
         }
         int nr = classify(g, e.p, e.d, e.region);
@@ -865,6 +936,12 @@ int orc_map_hu(const int16_t *hu, uint64_t n, int n_pts, const double *ch, const
 
 int orc_run(const orc_config *cf, uint64_t first, uint64_t count, double *sum, double *sum2, orc_counters *cnt)
 {
+    return orc_run_traced(cf, first, count, sum, sum2, cnt, NULL, 0, NULL);
+}
+
+int orc_run_traced(const orc_config *cf, uint64_t first, uint64_t count, double *sum, double *sum2, orc_counters *cnt,
+                   orc_event *ev, uint64_t cap, uint64_t *n_ev)
+{
     if (!cf || !sum || !sum2 || !cnt || cf->n_layers < 1 || cf->n_layers > ORC_MAX_LAYERS || cf->n_mat < 1) return ORC_E_ARG;
     pthread_once(&gl_once, gl_init);
     geo_t g;
@@ -885,7 +962,11 @@ int orc_run(const orc_config *cf, uint64_t first, uint64_t count, double *sum, d
     c->hacc = (double *)calloc(npix, sizeof(double));
     c->touched = (int *)malloc(sizeof(int) * (size_t)npix);
     c->cnt = cnt;
+    c->ev = ev;
+    c->ev_cap = ev ? cap : 0;
+    c->ev_n = 0;
     for (uint64_t h = first; h < first + count && !c->err; ++h) {
+        c->hist = h;
         orng_init(&c->rng, cf->seed, h);
         c->n = 0; c->ntouched = 0; c->dep = 0; c->esc = 0; c->rest = 0;
         part_t src;
@@ -917,6 +998,7 @@ int orc_run(const orc_config *cf, uint64_t first, uint64_t count, double *sum, d
         }
     }
     int err = c->err;
+    if (n_ev) *n_ev = c->ev_n;
     free(c->hacc); free(c->touched); free(c); free(g.mu_cache);
     return err;
 }

@@ -83,6 +83,9 @@ typedef struct {
     uint64_t n_phsp;          /* >0: phase-space list replaces spectrum and aperture */
     const double *phsp;       /* [n_phsp][8]: x y z u v w E type(0 photon, 1 e-, 2 e+) */
     uint64_t seed;
+    double   step_floor;      /* a boundary-limited electron step is at least this fraction of the
+                                 cell's smallest dimension; the reading is 0 (a step never crosses
+                                 a face); other values only serve to measure what a floor does */
 } orc_config;
 
 typedef struct {
@@ -98,6 +101,34 @@ typedef struct {
     double   max_ledger_resid;      /* max over histories of |ledger residual| / E_in */
 } orc_counters;
 
+/* One record of the optional event trace (orc_run_traced), in the order the events happen.
+ * Units cm, MeV.  Fields that a kind does not use are zero.
+ *   ORC_EV_DEPOSIT  energy E0 left at pos in `region` (0 phantom, 1 EPID, -1 outside both);
+ *                   layer = EPID layer or -1; pixel = image index it was tallied to, or -1
+ *   ORC_EV_ESTEP    condensed-history step from pos along d0 over aux[0] cm (aux[1] g/cm^2),
+ *                   kinetic energy E0 -> E1 (continuous loss), direction after it d1, hinge
+ *                   point dc[0]; Ec[0] = radiation length X0 (g/cm^2) of its medium
+ *   ORC_EV_COMPTON  photon E0 d0 -> E1 d1 at pos, electron Ec[0] along dc[0]
+ *   ORC_EV_PHOTO    photon E0 d0 absorbed at pos, electron Ec[0] along dc[0]
+ *   ORC_EV_PAIR     photon E0 d0 at pos -> electron Ec[0] dc[0], positron Ec[1] dc[1]
+ *   ORC_EV_ANNIH    positron at rest at pos -> photons Ec[0] dc[0], Ec[1] dc[1]
+ *   ORC_EV_MOLLER   electron E0 d0 -> E1 d1 at pos, delta ray Ec[0] dc[0]
+ *   ORC_EV_BREMS    electron E0 d0 -> E1 d1 at pos, photon Ec[0] dc[0]
+ *   ORC_EV_NULL     a sampled hard-event site rejected as fictitious at pos, energy E0 */
+enum { ORC_EV_DEPOSIT = 0, ORC_EV_ESTEP, ORC_EV_COMPTON, ORC_EV_PHOTO, ORC_EV_PAIR, ORC_EV_ANNIH,
+       ORC_EV_MOLLER, ORC_EV_BREMS, ORC_EV_NULL };
+
+typedef struct {
+    uint64_t hist;
+    int32_t  kind, region, layer, pixel;
+    double   pos[3];
+    double   E0, E1;
+    double   d0[3], d1[3];
+    double   Ec[2];
+    double   dc[2][3];
+    double   aux[2];
+} orc_event;
+
 /* Return codes */
 #define ORC_OK        0
 #define ORC_E_ARG    -1
@@ -107,6 +138,11 @@ typedef struct {
  * for every pixel p = v*npx_u + u (caller zeroes the arrays).  cnt is accumulated into. */
 int orc_run(const orc_config *cfg, uint64_t first, uint64_t count,
             double *sum, double *sum2, orc_counters *cnt);
+
+/* orc_run that also records every event into ev[0 .. cap) (see orc_event) and returns the
+ * number recorded in *n_ev; events beyond cap are counted in *n_ev but not stored. */
+int orc_run_traced(const orc_config *cfg, uint64_t first, uint64_t count,
+                   double *sum, double *sum2, orc_counters *cnt, orc_event *ev, uint64_t cap, uint64_t *n_ev);
 
 /* source particle of history h: x y z u v w E type */
 int orc_source(const orc_config *cfg, uint64_t h, double out[8]);
@@ -127,6 +163,9 @@ double orc_lres(const orc_material *m, double T, double wcut, double kcut);   /*
 double orc_sigma_moller(const orc_material *m, double T, double wcut);      /* cm^2/g */
 double orc_sigma_brems(const orc_material *m, double T, double kcut);       /* cm^2/g */
 double orc_moller_sample(double T, double wcut, double xi);                 /* W (MeV) */
+double orc_srad(const orc_material *m, double T);                           /* radiative stopping power */
+double orc_brems_sample(double T, double kcut, double xi);                  /* photon energy k (MeV) */
+double orc_sigma_hard_max(const orc_material *m, double T0, double wcut, double kcut); /* cm^2/g */
 double orc_range_diff(const orc_material *m, double T_lo, double T_hi, double wcut, double kcut); /* g/cm^2 */
 double orc_range_inverse(const orc_material *m, double T0, double dR, double wcut, double kcut);
 double orc_x0(const orc_material *m);                 /* radiation length, g/cm^2 */

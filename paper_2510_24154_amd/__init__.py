@@ -81,7 +81,8 @@ EXPORTS = [
     "epidmc_workspace_size", "epidmc_bind_workspace", "epidmc_run", "epidmc_run_until", "epidmc_read_image",
     "epidmc_sigma_bar", "epidmc_reset_tally", "epidmc_get_counters",
     "epidmc_radiological_thickness", "epidmc_field_size", "epidmc_dose_response",
-    "epidmc_debug_philox", "epidmc_debug_sample", "epidmc_debug_table",
+    "epidmc_resample_response_table",
+    "epidmc_debug_philox", "epidmc_debug_sample", "epidmc_debug_table", "epidmc_debug_records",
 ] + DN_EXPORTS
 
 _lib = None
@@ -121,9 +122,11 @@ def load_library(path: str = LIB_PATH):
         "epidmc_radiological_thickness": [vp, vp, vp],
         "epidmc_field_size": [vp, ct.POINTER(f64)],
         "epidmc_dose_response": [vp, vp, vp, f64, vp, i32, vp, i32, vp, vp, vp],
+        "epidmc_resample_response_table": [vp, i32, vp, i32, vp, vp, i32, vp, i32, vp],
         "epidmc_debug_philox": [vp, vp, vp, u64, vp],
         "epidmc_debug_sample": [vp, i32, f64, f64, f64, vp, u64, vp],
         "epidmc_debug_table": [vp, i32, i32, vp, vp, u64, vp],
+        "epidmc_debug_records": [vp, vp, vp, u64, ct.POINTER(u64), vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -354,6 +357,18 @@ class Engine:
                                                ct.c_void_p(out.data_ptr()), int(n), self._stream()))
         return out.cpu().numpy().reshape(n, width) if width > 1 else out.cpu().numpy()
 
+    def debug_records(self, cap):
+        """Kahan-mode deposit records of the last chunk: (image element, MeV) as numpy arrays
+        and the chunk's record count."""
+        t = self.torch
+        pix = t.empty(max(1, cap), dtype=t.int32, device=self.device)
+        e = t.empty(max(1, cap), dtype=t.float32, device=self.device)
+        n = ct.c_uint64()
+        self._check(self.L.epidmc_debug_records(self.h, ct.c_void_p(pix.data_ptr()), ct.c_void_p(e.data_ptr()), int(cap),
+                                                ct.byref(n), self._stream()))
+        k = min(cap, n.value)
+        return pix[:k].cpu().numpy().view(np.uint32), e[:k].cpu().numpy(), n.value
+
     def debug_table(self, kind, index, energies):
         t = self.torch
         E = t.as_tensor(np.asarray(energies, dtype=np.float32), device=self.device).contiguous()
@@ -361,3 +376,20 @@ class Engine:
         self._check(self.L.epidmc_debug_table(self.h, int(kind), int(index), ct.c_void_p(E.data_ptr()),
                                               ct.c_void_p(out.data_ptr()), E.numel(), self._stream()))
         return out.cpu().numpy()
+
+
+def resample_response_table(t_nodes, s_nodes, k, t_out, s_out):
+    """k(t, s) resampled onto the nodes t_out x s_out (epidmc_resample_response_table, host
+    code of the engine): returns k_out[j][i] at (t_out[i], s_out[j])."""
+    L = load_library()
+    tn = np.ascontiguousarray(t_nodes, dtype=np.float64)
+    sn = np.ascontiguousarray(s_nodes, dtype=np.float64)
+    kk = np.ascontiguousarray(k, dtype=np.float64).reshape(sn.size, tn.size)
+    to = np.ascontiguousarray(t_out, dtype=np.float64)
+    so = np.ascontiguousarray(s_out, dtype=np.float64)
+    out = np.empty((so.size, to.size), dtype=np.float64)
+    st = L.epidmc_resample_response_table(tn.ctypes.data, tn.size, sn.ctypes.data, sn.size, kk.ctypes.data,
+                                          to.ctypes.data, to.size, so.ctypes.data, so.size, out.ctypes.data)
+    if st != 0:
+        raise ValueError(f"epidmc_resample_response_table failed: status {st}")
+    return out

@@ -51,8 +51,6 @@ constexpr double BREM_K = 800.0;             // S_rad/S_col = Z_eff T / 800 MeV
 constexpr double WCUT = 0.200;               // hard Moller threshold, MeV
 constexpr double KCUT = 0.010;               // hard bremsstrahlung threshold, MeV
 constexpr float NUDGE = 1.0e-5f;             // cm past a boundary for boundary-limited steps
-constexpr float SKIN = 0.05f;                // a boundary-limited step is at least this fraction of the
-                                             // cell's smallest dimension
 constexpr float DE_FRAC = 0.9f;              // a step keeps at least 90% of its start energy
 constexpr int MAX_E_STEPS = 100000;          // per electron and launch; more is an error
 
@@ -84,14 +82,12 @@ struct Params {
     float chord;                // longer than any straight path inside the box
     double ddx, ddy, ddz;       // voxel spacing in FP64 (electron positions are FP64)
     double iddx, iddy, iddz;    // and its inverse
-    float smin_ph;              // minimum boundary-limited electron step in the phantom
     const uint32_t *vox;        // packed density (bits 31..2) | material (bits 1..0)
 
     // EPID, local frame: x, y global, z from the front face
     int nl, scoring;
     float zl[MAX_LAYERS + 1];
     float lrho[MAX_LAYERS];
-    float lsmin[MAX_LAYERS];    // minimum boundary-limited electron step per layer
     float front_z, hx, hy;      // front face (global z), lateral half extents
     float zback;                // back face of the last layer (local z)
     int npx_u, npx_v;

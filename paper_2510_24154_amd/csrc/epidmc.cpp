@@ -34,6 +34,7 @@ hipError_t launch_dbg_sample(const Params &P, int kind, float p0, float p1, floa
                              unsigned long long n, hipStream_t s);
 hipError_t launch_dbg_table(const Params &P, int kind, int index, const float *E, float *out, unsigned long long n,
                             hipStream_t s);
+hipError_t launch_dbg_source(const Params &P, unsigned long long h0, float *out, unsigned long long n, hipStream_t s);
 }  // namespace epidmc
 
 using namespace epidmc;
@@ -118,6 +119,7 @@ struct epidmc_ctx {
     hipEvent_t go = nullptr, done[NQ] = {};
     double kernel_ms[NQ] = {0, 0, 0, 0};
     uint64_t kernel_launches[NQ] = {0, 0, 0, 0};
+    uint32_t last_nrec = 0;         // Kahan mode: records of the last chunk
     // accumulated
     double n_total = 0, b_total = 0;
     uint64_t launches = 0, queue_peak = 0;
@@ -699,7 +701,6 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
     P.chord = P.Lx + P.Ly + P.Lz + 1.0f;
     P.ddx = c->spacing[0]; P.ddy = c->spacing[1]; P.ddz = c->spacing[2];
     P.iddx = 1.0 / P.ddx; P.iddy = 1.0 / P.ddy; P.iddz = 1.0 / P.ddz;
-    P.smin_ph = SKIN * std::min(c->spacing[0], std::min(c->spacing[1], c->spacing[2]));
     P.vox = (const uint32_t *)(w + L.vox.off);
     P.nl = (int)c->layers.size();
     P.scoring = c->scoring;
@@ -709,7 +710,6 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
         z += c->layers[l].thickness;
         P.zl[l + 1] = (float)z;
         P.lrho[l] = c->layers[l].density;
-        P.lsmin[l] = SKIN * c->layers[l].thickness;
     }
     for (int l = P.nl + 1; l <= MAX_LAYERS; ++l) P.zl[l] = (float)z;
     P.zback = (float)z;
@@ -902,6 +902,7 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
         HIPCHK(hipMemcpyAsync(c->host, cnt + 3 * NQ, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const uint32_t nrec = std::min(c->host[0], c->lay.rec_cap);
+        c->last_nrec = nrec;
         const uint32_t nimg = (uint32_t)((size_t)c->lay.ring * P.npix);
         HIPCHK(launch_kahan_reduce(P, nrec, nimg, (uint32_t *)(c->ws + c->lay.k_count.off),
                                    (uint32_t *)(c->ws + c->lay.k_cursor.off), (uint32_t *)(c->ws + c->lay.k_bsum.off),
@@ -1029,6 +1030,7 @@ extern "C" epidmc_status epidmc_reset_tally(epidmc_ctx *c, void *stream)
     c->b_total = 0;
     c->launches = 0;
     c->queue_peak = 0;
+    c->last_nrec = 0;
     for (int k = 0; k < NQ; ++k) { c->kernel_ms[k] = 0; c->kernel_launches[k] = 0; }
     return EPIDMC_OK;
 }
@@ -1162,6 +1164,47 @@ extern "C" epidmc_status epidmc_dose_response(epidmc_ctx *c, const double *dev_i
     return EPIDMC_OK;
 }
 
+// clamped bilinear k(t, s) on a rectilinear table (the evaluation k_response performs on
+// the device, with s fixed per field)
+static double table_bilinear(const double *tn, int nt, const double *sn, int ns, const double *k, double t, double s)
+{
+    auto bracket = [](const double *x, int n, double v, int &i, double &f) {
+        i = 0;
+        f = 0.0;
+        if (n == 1 || v <= x[0]) return;
+        if (v >= x[n - 1]) { i = n - 2; f = 1.0; return; }
+        while (i + 1 < n - 1 && v >= x[i + 1]) ++i;
+        f = (v - x[i]) / (x[i + 1] - x[i]);
+    };
+    int i, j;
+    double ft, fs;
+    bracket(tn, nt, t, i, ft);
+    bracket(sn, ns, s, j, fs);
+    const int i1 = nt > 1 ? i + 1 : i, j1 = ns > 1 ? j + 1 : j;
+    const double r0 = (1.0 - ft) * k[j * nt + i] + ft * k[j * nt + i1];
+    const double r1 = (1.0 - ft) * k[j1 * nt + i] + ft * k[j1 * nt + i1];
+    return (1.0 - fs) * r0 + fs * r1;
+}
+
+extern "C" epidmc_status epidmc_resample_response_table(const double *tn, int nt, const double *sn, int ns, const double *k,
+                                                        const double *to, int mt, const double *so, int ms, double *ko)
+{
+    if (!tn || !sn || !k || !to || !so || !ko) return EPIDMC_E_ARG;
+    if (nt < 1 || nt > RESP_MAX || ns < 1 || ns > RESP_MAX || mt < 1 || mt > RESP_MAX || ms < 1 || ms > RESP_MAX)
+        return EPIDMC_E_RANGE;
+    auto ascending = [](const double *x, int n) {
+        for (int i = 0; i < n; ++i)
+            if (!std::isfinite(x[i]) || (i > 0 && !(x[i] > x[i - 1]))) return false;
+        return true;
+    };
+    if (!ascending(tn, nt) || !ascending(sn, ns) || !ascending(to, mt) || !ascending(so, ms)) return EPIDMC_E_RANGE;
+    for (int q = 0; q < nt * ns; ++q)
+        if (!std::isfinite(k[q])) return EPIDMC_E_RANGE;
+    for (int j = 0; j < ms; ++j)
+        for (int i = 0; i < mt; ++i) ko[j * mt + i] = table_bilinear(tn, nt, sn, ns, k, to[i], so[j]);
+    return EPIDMC_OK;
+}
+
 extern "C" epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *ctr, uint32_t *out, uint64_t n, void *stream)
 {
     if (!c || !ctr || !out || n == 0) return EPIDMC_E_ARG;
@@ -1186,7 +1229,36 @@ extern "C" epidmc_status epidmc_debug_sample(epidmc_ctx *c, int kind, double p0,
     if (kind == 2) REQUIRE(p0 > KCUT && p0 <= 50, EPIDMC_E_RANGE, "bremsstrahlung needs T > 10 keV");
     if (kind == 3) REQUIRE(p0 > 0 && p1 >= 0 && p2 > 0, EPIDMC_E_RANGE, "scattering arguments");
     HIPCHK(hipSetDevice(c->device));
+    if (kind == 4) {
+        // history ids are integers below 2^53 here; the key takes the high-word mix that
+        // run_chunk applies, so the probe draws exactly what k_source draws
+        REQUIRE(p0 >= 0 && p0 < 9007199254740992.0 && p0 == std::floor(p0), EPIDMC_E_RANGE,
+                "source probe: first history must be a non-negative integer below 2^53");
+        const uint64_t h0 = (uint64_t)p0;
+        REQUIRE((h0 >> 32) == ((h0 + n - 1) >> 32), EPIDMC_E_RANGE, "source probe range spans a 2^32 boundary");
+        const uint32_t hi = (uint32_t)(h0 >> 32);
+        P.key0 ^= hi * 0x9E3779B9u;
+        P.key1 ^= hi * 0x85EBCA6Bu;
+        HIPCHK(launch_dbg_source(P, h0, out, n, (hipStream_t)stream));
+        return EPIDMC_OK;
+    }
     HIPCHK(launch_dbg_sample(P, kind, (float)p0, (float)p1, (float)p2, out, n, (hipStream_t)stream));
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_debug_records(epidmc_ctx *c, uint32_t *dev_pix, float *dev_e, uint64_t cap, uint64_t *n,
+                                              void *stream)
+{
+    if (!c || !n || (cap > 0 && (!dev_pix || !dev_e))) return fail(c, EPIDMC_E_ARG, "null argument");
+    REQUIRE(c->bound && c->tally_mode == 2, EPIDMC_E_NOT_READY, "records exist in the Kahan tally mode only");
+    REQUIRE(c->n_total > 0, EPIDMC_E_NOT_READY, "no histories run");
+    *n = c->last_nrec;
+    const uint64_t k = std::min<uint64_t>(cap, c->last_nrec);
+    if (k == 0) return EPIDMC_OK;
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(dev_pix, c->P.rec_pix, k * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(dev_e, c->P.rec_e, k * 4, hipMemcpyDeviceToDevice, s));
     return EPIDMC_OK;
 }
 

@@ -306,6 +306,12 @@ __device__ __forceinline__ float moller_sample(const Params &P, Part &p, float T
     return eps * T;
 }
 
+// bremsstrahlung photon energy from the 1/k spectrum on [KCUT, T]: k = KCUT (T / KCUT)^u
+__device__ __forceinline__ float brems_k(float T, float u)
+{
+    return (float)KCUT * __expf(u * __logf(T * (float)(1.0 / KCUT)));
+}
+
 // Highland width (unit charge) for kinetic energy T over x g/cm^2 of radiation length X0
 __device__ __forceinline__ float highland(float T, float x, float X0)
 {
@@ -362,56 +368,69 @@ __device__ __forceinline__ void pair_produce(const Params &P, int region, Part &
 // ---------------------------------------------------------------------------------
 // source: one thread per history
 // ---------------------------------------------------------------------------------
+// The source particle of history h in the global frame, a stand-in for the particles that
+// leave the collimators (Sec. 2.1.1): particle h mod n of a phase-space list, or a photon
+// whose energy comes from the spectrum's alias table and whose direction aims at a point
+// drawn uniformly over the open area of the history's segment (a leaf pair from the
+// segment's alias table over open widths, then a point uniform within the pair).  The
+// history's random stream starts at draw 0 with particle id 0.
+__device__ __forceinline__ void source_particle(const Params &P, unsigned long long h, Part &p, float &gx, float &gy,
+                                                float &gz, uint32_t &type)
+{
+    p.hist = (uint32_t)h;
+    p.plo = 0; p.phi = 0; p.draw = 0;
+    type = 0;
+    if (P.n_phsp) {
+        const float *q = P.phsp + 8 * (h % P.n_phsp);
+        gx = q[0]; gy = q[1]; gz = q[2];
+        p.u = q[3]; p.v = q[4]; p.w = q[5];
+        p.E = q[6];
+        type = (uint32_t)q[7];
+        return;
+    }
+    const float4 r = rnd4(p, P);
+    int i = min((int)(r.x * (float)P.nbins), P.nbins - 1);
+    if (r.y >= P.sp_prob[i]) i = P.sp_alias[i];
+    p.E = fmaf(r.z, P.sp_hi[i] - P.sp_lo[i], P.sp_lo[i]);
+    int s = 0;
+    if (P.n_seg > 1) {
+        int lo = 0, hi = P.n_seg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (h < P.seg_end[mid]) hi = mid; else lo = mid + 1;
+        }
+        s = lo;
+    }
+    const float4 r2 = rnd4(p, P);
+    const int base = s * P.n_pairs;
+    int k = min((int)(r2.x * (float)P.n_pairs), P.n_pairs - 1);
+    if (r2.y >= P.ap_prob[base + k]) k = P.ap_alias[base + k];
+    const float a = P.ap_a[base + k], b = P.ap_b[base + k];
+    const float x = fmaf(r2.z, b - a, a);
+    const float y = fmaf((float)k + r2.w, P.leaf_w, P.y0);
+    if (P.beam_kind == 0) {
+        gx = x; gy = y; gz = P.src[2];
+        p.u = 0.0f; p.v = 0.0f; p.w = 1.0f;
+    } else {
+        const float dx = x - P.src[0], dy = y - P.src[1], dz = P.iso_z - P.src[2];
+        const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+        gx = P.src[0]; gy = P.src[1]; gz = P.src[2];
+        p.u = dx * inv; p.v = dy * inv; p.w = dz * inv;
+    }
+}
+
 __global__ __launch_bounds__(WG) void k_source(Params P)
 {
     Local L;
     zero(L);
     const unsigned long long h = P.h0 + (unsigned long long)blockIdx.x * WG + threadIdx.x;
     const bool live = h < P.h1;
-    Part p;
-    p.hist = (uint32_t)h;
-    p.plo = 0; p.phi = 0; p.draw = 0;
-    float gx = 0, gy = 0, gz = 0;
     if (live) {
         const uint32_t slot = (uint32_t)(((h - P.run_first) * (unsigned long long)P.run_batches / P.run_n) % P.ring);
+        Part p;
+        float gx = 0, gy = 0, gz = 0;
         uint32_t type = 0;
-        if (P.n_phsp) {
-            const float *q = P.phsp + 8 * (h % P.n_phsp);
-            gx = q[0]; gy = q[1]; gz = q[2];
-            p.u = q[3]; p.v = q[4]; p.w = q[5];
-            p.E = q[6];
-            type = (uint32_t)q[7];
-        } else {
-            const float4 r = rnd4(p, P);
-            int i = min((int)(r.x * (float)P.nbins), P.nbins - 1);
-            if (r.y >= P.sp_prob[i]) i = P.sp_alias[i];
-            p.E = fmaf(r.z, P.sp_hi[i] - P.sp_lo[i], P.sp_lo[i]);
-            int s = 0;
-            if (P.n_seg > 1) {
-                int lo = 0, hi = P.n_seg - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (h < P.seg_end[mid]) hi = mid; else lo = mid + 1;
-                }
-                s = lo;
-            }
-            const float4 r2 = rnd4(p, P);
-            const int base = s * P.n_pairs;
-            int k = min((int)(r2.x * (float)P.n_pairs), P.n_pairs - 1);
-            if (r2.y >= P.ap_prob[base + k]) k = P.ap_alias[base + k];
-            const float a = P.ap_a[base + k], b = P.ap_b[base + k];
-            const float x = fmaf(r2.z, b - a, a);
-            const float y = fmaf((float)k + r2.w, P.leaf_w, P.y0);
-            if (P.beam_kind == 0) {
-                gx = x; gy = y; gz = P.src[2];
-                p.u = 0.0f; p.v = 0.0f; p.w = 1.0f;
-            } else {
-                const float dx = x - P.src[0], dy = y - P.src[1], dz = P.iso_z - P.src[2];
-                const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
-                gx = P.src[0]; gy = P.src[1]; gz = P.src[2];
-                p.u = dx * inv; p.v = dy * inv; p.w = dz * inv;
-            }
-        }
+        source_particle(P, h, p, gx, gy, gz, type);
         p.flags = (slot << F_SLOT_SHIFT) | type | (type == 0 ? F_UNSCAT : 0u);
         if (P.diag) P.ein[h - P.h0] = (double)p.E;
         p.x = gx - P.ox; p.y = gy - P.oy; p.z = gz - P.oz;
@@ -746,7 +765,7 @@ template <bool EPID>
 __global__ __launch_bounds__(WG) void k_electron(Params P)
 {
     extern __shared__ __align__(16) float lds[];
-    __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS], s_smin[MAX_LAYERS], s_x0[MAX_PMAT + MAX_LAYERS];
+    __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS], s_x0[MAX_PMAT + MAX_LAYERS];
     const int nm = EPID ? P.nl : P.nmat_ph;
     const float *src = P.el_tab + (EPID ? MAX_PMAT : 0) * 3 * NB_EL;
     for (int i = threadIdx.x; i < nm * 3 * NB_EL; i += WG) lds[i] = src[i];
@@ -756,10 +775,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
     Stages S;
     stage_carve(S, (uint32_t *)(lds + nm * 3 * NB_EL) + wave_id() * nstage * stage_words(SBUF_E), smask, SBUF_E);
     if (threadIdx.x <= MAX_LAYERS) s_zl[threadIdx.x] = P.zl[threadIdx.x];
-    if (threadIdx.x < MAX_LAYERS) {
-        s_rho[threadIdx.x] = P.lrho[threadIdx.x];
-        s_smin[threadIdx.x] = P.lsmin[threadIdx.x];
-    }
+    if (threadIdx.x < MAX_LAYERS) s_rho[threadIdx.x] = P.lrho[threadIdx.x];
     if (threadIdx.x < MAX_PMAT + MAX_LAYERS) s_x0[threadIdx.x] = P.el_x0[threadIdx.x];
     __syncthreads();
     const int kind = EPID ? QEE : QEP;
@@ -777,6 +793,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
     int nsteps = 0;
     int hpend = 0;   // a hard event pending at p: 1 process not chosen yet, 2 a Moller sample to retry
     int hmat = 0;    // the medium of the step that ended in it
+    float hsig = 0.0f;   // the hard cross section its distance was drawn against
     unsigned long long lane_iters = 0, wave_iters = 0;
     for (;;) {
         stage_flush_all(P, S, SBUF_E / 2);
@@ -811,7 +828,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
         if (hpend == 0) {
             ++L.steps;
             // current cell and medium
-            float rho, smin;
+            float rho;
             double lo0, hi0, lo1, hi1, lo2, hi2;
             int m, layer = -1;
             if (!EPID) {
@@ -824,7 +841,6 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                 lo0 = ix * P.ddx; hi0 = lo0 + P.ddx;
                 lo1 = iy * P.ddy; hi1 = lo1 + P.ddy;
                 lo2 = iz * P.ddz; hi2 = lo2 + P.ddz;
-                smin = P.smin_ph;
             } else {
                 int l = 0;
 #pragma unroll
@@ -835,7 +851,6 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                 rho = s_rho[l];
                 lo0 = -P.hx; hi0 = P.hx; lo1 = -P.hy; hi1 = P.hy;
                 lo2 = s_zl[l]; hi2 = s_zl[l + 1];
-                smin = s_smin[l];
             }
             // distance to the cell faces: the offset to the face is taken in FP64, then the small
             // difference is divided in FP32
@@ -843,7 +858,9 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
             if (p.u != 0.0f) dg = fminf(dg, (float)((p.u > 0.0f ? hi0 : lo0) - px) / p.u);
             if (p.v != 0.0f) dg = fminf(dg, (float)((p.v > 0.0f ? hi1 : lo1) - py) / p.v);
             if (p.w != 0.0f) dg = fminf(dg, (float)((p.w > 0.0f ? hi2 : lo2) - pz) / p.w);
-            const float sg = fmaxf(fmaxf(dg, 0.0f) + NUDGE, smin);
+            // a boundary-limited step ends just past the face, so that it never carries this
+            // cell's medium into the next one
+            const float sg = fmaxf(dg, 0.0f) + NUDGE;
             settle = true;
             if (!(rho > 0.0f)) {
                 px += (double)sg * p.u;
@@ -854,9 +871,13 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                 const float lnT = __logf(T);
                 const Node n0 = node_of(lnT, P.el_lnT0, P.el_idl, NB_EL);
                 const float R0 = lerp_tab(tab, n0);
-                const float sh = lerp_tab(tab + NB_EL, n0);
                 const Node n9 = node_of(lnT + ln09, P.el_lnT0, P.el_idl, NB_EL);
                 const float R9 = lerp_tab(tab, n9);
+                // the distance to a hard event is drawn against the largest hard cross section
+                // over the energies this step can reach, [0.9 T0, T0]: the cross section falls
+                // and then rises with T, so the larger end value bounds it; the event at the
+                // step's end is then real with probability sigma(T1) / sh
+                const float sh = fmaxf(lerp_tab(tab + NB_EL, n0), lerp_tab(tab + NB_EL, n9));
                 const float s_hard = sh > 0.0f ? -__logf(r.x) / (rho * sh) : INFINITY;
                 const float s_de = (R0 - R9) / rho;
                 const float s_pix = (EPID && layer == P.scoring) ? P.s_pix : INFINITY;
@@ -877,14 +898,15 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                     const float f = d > 0.0f ? fminf(fmaxf((Rt - tab[lo]) / d, 0.0f), 1.0f) : 0.0f;
                     T1 = fminf(__expf(P.el_lnT0 + ((float)lo + f) / P.el_idl), T);
                 }
-                // hinge point: the step's continuous loss is deposited there
+                // hinge point: the step's continuous loss is deposited there, in the layer that
+                // holds it
                 const double a = (double)(r.y * s);
                 px += a * p.u;
                 py += a * p.v;
                 pz += a * p.w;
                 const float dep = T - T1;
                 if (P.diag) ledger(P, p.hist, (double)T - (double)T1);
-                if (EPID && layer == P.scoring) {
+                if (EPID && pz >= (double)s_zl[P.scoring] && pz < (double)s_zl[P.scoring + 1]) {
                     tally(P, p.flags, (float)px, (float)py, dep);
                     ++L.tally;
                 }
@@ -905,6 +927,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                     // the event itself takes the next draw, with the rest of the wave
                     hpend = 1;
                     hmat = m;
+                    hsig = sh;
                     settle = false;
                 }
             }
@@ -914,13 +937,22 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
             const float *tab = lds + hmat * 3 * NB_EL;
             bool moller = hpend == 2;
             float u1 = r.x, u2 = r.y, uphi = r.z;   // a retried Moller trial
+            bool real = true;
             if (hpend == 1) {
+                // real with probability sigma(T1) / hsig; the same uniform picks the process
                 const Node n1 = node_of(__logf(T), P.el_lnT0, P.el_idl, NB_EL);
-                moller = r.x < lerp_tab(tab + 2 * NB_EL, n1) && T > 2.0f * (float)WCUT;
-                if (moller) ++L.moller; else ++L.brems;
+                const float sig1 = lerp_tab(tab + NB_EL, n1), fm = lerp_tab(tab + 2 * NB_EL, n1);
+                const float sm1 = T > 2.0f * (float)WCUT ? sig1 * fm : 0.0f;   // no Moller event below 2 WCUT
+                const float u = r.x * hsig;
+                moller = u < sm1;
+                real = u < sm1 + (sig1 - sig1 * fm);
+                if (moller) ++L.moller; else if (real) ++L.brems;
                 u1 = r.y; u2 = r.z; uphi = r.w;
             }
-            if (moller) {
+            if (!real) {
+                hpend = 0;   // a fictitious event: the electron goes on unchanged
+                settle = true;
+            } else if (moller) {
                 float eps;
                 if (moller_trial(moller_setup(T), u1, u2, eps)) {
                     const float W = eps * T, Tp = T - W;
@@ -943,7 +975,7 @@ __global__ __launch_bounds__(WG) void k_electron(Params P)
                     hpend = 2;
                 }
             } else {
-                const float k = (float)KCUT * __expf(u1 * __logf(T * (float)(1.0 / KCUT)));
+                const float k = brems_k(T, u1);
                 const float Tn = T - k;
                 if (P.diag) ledger(P, p.hist, (double)T - (double)Tn - (double)k);
                 T = Tn;
@@ -1037,9 +1069,13 @@ __global__ void k_fold(Params P, FoldArgs A)
     }
 }
 
-// Kahan mode: reduce deposit records into the slot images.  Records are binned by their
-// image index with a counting sort, then one thread per image element adds its records in
-// FP32 with Kahan compensation and writes the total (no atomics on the image).
+// Kahan mode: reduce deposit records into the slot images without atomics on the image, in
+// an order that does not depend on scheduling, so that the image is the same on every run.
+// Records are binned by image element with a counting sort (arbitrary order within an
+// element), each element's records are then put in ascending order (a canonical order of the
+// same multiset of values), and one workgroup per tile of KT consecutive elements streams the
+// tile's records through LDS while each thread adds its element's records in that order in
+// FP32 with Kahan compensation.
 __global__ void k_rec_count(const uint32_t *pix, uint32_t n, uint32_t *count)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -1086,19 +1122,64 @@ __global__ void k_rec_scatter(const uint32_t *pix, const float *e, uint32_t n, u
     }
 }
 
-__global__ void k_rec_kahan(const uint32_t *start, const uint32_t *end, const float *sorted, uint32_t nimg,
-                            double *img)
+// each element's records [start, end) into ascending order, in place (heapsort: no extra
+// memory, n log n even for a pixel that collects many records).  Deposits are positive, so
+// their bit patterns order like their values.
+__global__ void k_rec_order(const uint32_t *start, const uint32_t *end, float *sorted, uint32_t nimg)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nimg; i += gridDim.x * blockDim.x) {
-        float s = 0.0f, c = 0.0f;
-        for (uint32_t k = start[i]; k < end[i]; ++k) {
-            const float y = sorted[k] - c;
+        uint32_t *a = (uint32_t *)sorted + start[i];
+        const uint32_t n = end[i] - start[i];
+        if (n < 2) continue;
+        auto sift = [&](uint32_t root, uint32_t lim) {
+            const uint32_t v = a[root];
+            while (2 * root + 1 < lim) {
+                uint32_t ch = 2 * root + 1;
+                if (ch + 1 < lim && a[ch + 1] > a[ch]) ++ch;
+                if (a[ch] <= v) break;
+                a[root] = a[ch];
+                root = ch;
+            }
+            a[root] = v;
+        };
+        for (uint32_t r = n / 2; r-- > 0;) sift(r, n);
+        for (uint32_t m = n - 1; m > 0; --m) {
+            const uint32_t t = a[0];
+            a[0] = a[m];
+            a[m] = t;
+            sift(0, m);
+        }
+    }
+}
+
+constexpr int KT = 256;       // image elements per tile (one per thread)
+constexpr int KCHUNK = 2048;  // records staged in LDS per round
+
+// one workgroup per tile: the tile's records are contiguous, [start[t0], end[t0 + KT - 1]);
+// they pass through LDS in coalesced chunks and thread j adds those of element t0 + j
+__global__ __launch_bounds__(KT) void k_rec_kahan(const uint32_t *start, const uint32_t *end, const float *sorted,
+                                                  uint32_t nimg, double *img)
+{
+    __shared__ float chunk[KCHUNK];
+    const uint32_t t0 = blockIdx.x * KT, i = t0 + threadIdx.x;
+    const uint32_t last = min(t0 + KT, nimg) - 1;
+    const uint32_t b0 = start[t0], b1 = end[last];
+    const uint32_t my0 = i < nimg ? start[i] : 0, my1 = i < nimg ? end[i] : 0;
+    float s = 0.0f, c = 0.0f;
+    for (uint32_t base = b0; base < b1; base += KCHUNK) {
+        const uint32_t lim = min(base + (uint32_t)KCHUNK, b1);
+        __syncthreads();
+        for (uint32_t k = base + threadIdx.x; k < lim; k += KT) chunk[k - base] = sorted[k];
+        __syncthreads();
+        const uint32_t lo = max(my0, base), hi = min(my1, lim);
+        for (uint32_t k = lo; k < hi; ++k) {
+            const float y = chunk[k - base] - c;
             const float t = s + y;
             c = (t - s) - y;
             s = t;
         }
-        img[i] += (double)s - (double)c;
     }
+    if (i < nimg && my1 > my0) img[i] += (double)s - (double)c;
 }
 
 __global__ void k_image(Params P, double n, double nbatch, double *mean, double *var)
@@ -1331,7 +1412,7 @@ __global__ void k_dbg_sample(Params P, int kind, float p0, float p1, float p2, f
         out[i] = moller_sample(P, p, p0, phu);
     } else if (kind == 2) {
         const float4 r = rnd4(p, P);
-        out[i] = (float)KCUT * __expf(r.y * __logf(p0 * (float)(1.0 / KCUT)));
+        out[i] = brems_k(p0, r.y);
     } else if (kind == 3) {
         const float4 r = rnd4(p, P);
         out[i] = highland(p0, p1, p2) * sqrtf(-2.0f * __logf(r.z));
@@ -1351,46 +1432,18 @@ __global__ void k_dbg_table(Params P, int kind, int index, const float *E, float
     }
 }
 
-// source probe: the source kernel's sampling without transport
+// source probe: the source kernel's own sampling function without transport, for histories
+// [h0, h0 + n) (P's key already carries the high-word mix of h0)
 __global__ void k_dbg_source(Params P, unsigned long long h0, float *out, unsigned long long n)
 {
     const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const unsigned long long h = h0 + i;
     Part p;
-    p.hist = (uint32_t)h; p.plo = 0; p.phi = 0; p.draw = 0;
-    float gx, gy, gz;
-    const float4 r = rnd4(p, P);
-    int b = min((int)(r.x * (float)P.nbins), P.nbins - 1);
-    if (r.y >= P.sp_prob[b]) b = P.sp_alias[b];
-    p.E = fmaf(r.z, P.sp_hi[b] - P.sp_lo[b], P.sp_lo[b]);
-    int s = 0;
-    if (P.n_seg > 1) {
-        int lo = 0, hi = P.n_seg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (h < P.seg_end[mid]) hi = mid; else lo = mid + 1;
-        }
-        s = lo;
-    }
-    const float4 r2 = rnd4(p, P);
-    const int base = s * P.n_pairs;
-    int k = min((int)(r2.x * (float)P.n_pairs), P.n_pairs - 1);
-    if (r2.y >= P.ap_prob[base + k]) k = P.ap_alias[base + k];
-    const float a = P.ap_a[base + k], bb = P.ap_b[base + k];
-    const float x = fmaf(r2.z, bb - a, a);
-    const float y = fmaf((float)k + r2.w, P.leaf_w, P.y0);
-    if (P.beam_kind == 0) {
-        gx = x; gy = y; gz = P.src[2];
-        p.u = 0.0f; p.v = 0.0f; p.w = 1.0f;
-    } else {
-        const float dx = x - P.src[0], dy = y - P.src[1], dz = P.iso_z - P.src[2];
-        const float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
-        gx = P.src[0]; gy = P.src[1]; gz = P.src[2];
-        p.u = dx * inv; p.v = dy * inv; p.w = dz * inv;
-    }
+    float gx = 0, gy = 0, gz = 0;
+    uint32_t type = 0;
+    source_particle(P, h0 + i, p, gx, gy, gz, type);
     float *o = out + 8 * i;
-    o[0] = gx; o[1] = gy; o[2] = gz; o[3] = p.u; o[4] = p.v; o[5] = p.w; o[6] = p.E; o[7] = 0.0f;
+    o[0] = gx; o[1] = gy; o[2] = gz; o[3] = p.u; o[4] = p.v; o[5] = p.w; o[6] = p.E; o[7] = (float)type;
 }
 
 // ---------------------------------------------------------------------------------
@@ -1471,7 +1524,8 @@ hipError_t launch_kahan_reduce(const Params &P, uint32_t nrec, uint32_t nimg, ui
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rec_scatter, dim3(min(grid_for(nrec, 256), 8192u)), dim3(256), 0, s, P.rec_pix, P.rec_e,
                        nrec, cursor, sorted);
-    hipLaunchKernelGGL(k_rec_kahan, dim3(g), dim3(256), 0, s, count, cursor, sorted, nimg, (double *)P.img);
+    hipLaunchKernelGGL(k_rec_order, dim3(g), dim3(256), 0, s, count, cursor, sorted, nimg);
+    hipLaunchKernelGGL(k_rec_kahan, dim3(grid_for(nimg, KT)), dim3(KT), 0, s, count, cursor, sorted, nimg, (double *)P.img);
     return hipGetLastError();
 }
 
@@ -1536,11 +1590,17 @@ hipError_t launch_dbg_philox(const Params &P, const uint32_t *ctr, uint32_t *out
     return hipGetLastError();
 }
 
+hipError_t launch_dbg_source(const Params &P, unsigned long long h0, float *out, unsigned long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dbg_source, dim3(grid_for(n, 256)), dim3(256), 0, s, P, h0, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_dbg_sample(const Params &P, int kind, float p0, float p1, float p2, float *out,
                              unsigned long long n, hipStream_t s)
 {
     if (kind == 4) {
-        hipLaunchKernelGGL(k_dbg_source, dim3(grid_for(n, 256)), dim3(256), 0, s, P, (unsigned long long)p0, out, n);
+        return hipErrorInvalidValue;   // the source probe has its own launcher
     } else {
         hipLaunchKernelGGL(k_dbg_sample, dim3(grid_for(n, 256)), dim3(256), 0, s, P, kind, p0, p1, p2, out, n);
     }

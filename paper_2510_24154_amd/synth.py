@@ -270,6 +270,80 @@ def large_anthropomorphic(total=2_000_000_000, npx=(768, 1024), pitch=0.039):
     return cfg
 
 
+def large_crop(npx=64, pitch=0.312, field=6.0):
+    """A crop of the large case for transport parity with the oracle: the central 16 x 16 cm of
+    the anthropomorphic-like phantom over its full 20 cm depth, 1 mm voxels (160 x 160 x 200:
+    the spine, the inner lungs and the body wall), under an open field of `field` cm at the
+    isocentre, with the 4-layer EPID and a coarse image (64 x 64 pixels of 3.12 mm)."""
+    shape, sp = (160, 160, 200), (0.1, 0.1, 0.1)
+    cfg = coupled_hetero(shape=(8, 8, 8), npx=(npx, npx), pitch=pitch)
+    origin = (-0.5 * shape[0] * sp[0], -0.5 * shape[1] * sp[1], 100.0 - 0.5 * shape[2] * sp[2])
+    cfg["name"] = "large_crop"
+    cfg["phantom"] = {"kind": "hu", "shape": shape, "spacing": sp, "origin": origin,
+                      "hu": anthropomorphic_hu(shape, sp[0]),
+                      "curve": copy.deepcopy(HU_CURVE), "ranges": copy.deepcopy(HU_RANGES)}
+    cfg["source"]["aperture"] = _open_field(0.5 * field, 0.5 * field)
+    return cfg
+
+
+def narrow_field(field=1.0, npx=64, pitch=0.039):
+    """The coupled workload's phantom (256 x 256 x 128 voxels of 2 mm), spectrum and 4-layer
+    EPID at its native 0.39 mm pixels, under a narrow open field of `field` cm at the
+    isocentre onto an npx x npx image: an oracle run of a few million histories then gives
+    hundreds of phosphor deposits per in-field pixel."""
+    cfg = coupled_hetero(npx=(npx, npx), pitch=pitch)
+    cfg["name"] = "narrow_field"
+    cfg["source"]["aperture"] = _open_field(0.5 * field, 0.5 * field)
+    return cfg
+
+
+def phase_space_list(seed=8, n=8192, spectrum_seed=3):
+    """A seeded stand-in for a list of particles leaving the collimators (rows x y z u v w E
+    type; type 0 photon, 1 electron; cm, MeV) for the coupled workload's geometry: 75% photons
+    with energies from the 6 MV-like spectrum on rays from the point source through a uniform
+    point of the 10 x 10 cm field at the isocentre, starting on the plane z = 60 cm (above the
+    phantom box); 10% electrons of 1-6 MeV on such rays; 10% electrons of 0.3-4 MeV that start
+    inside the phantom (x, y within 5 cm of the axis, z 90-110 cm) in a forward direction; 5%
+    photons starting at z = 60 cm on rays that miss the phantom box."""
+    rng = np.random.default_rng(seed)
+    edges, w = thin_target_spectrum(spectrum_seed)
+    out = np.zeros((n, 8))
+    kind = rng.choice(4, size=n, p=[0.75, 0.10, 0.10, 0.05])
+    # rays from the source through the field: photons (0) and electrons (1)
+    ray = kind <= 1
+    px, py = rng.uniform(-5.0, 5.0, n), rng.uniform(-5.0, 5.0, n)
+    d = np.stack([px, py, np.full(n, 100.0)], axis=1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    t = 60.0 / d[:, 2]
+    out[ray, 0:3] = (d * t[:, None])[ray]
+    out[ray, 3:6] = d[ray]
+    # rays that miss the box: aimed outside |x| > 30 cm at z = 100
+    miss = kind == 3
+    mx = rng.choice([-1.0, 1.0], n) * rng.uniform(32.0, 40.0, n)
+    dm = np.stack([mx, rng.uniform(-5.0, 5.0, n), np.full(n, 100.0)], axis=1)
+    dm /= np.linalg.norm(dm, axis=1, keepdims=True)
+    out[miss, 0:3] = (dm * (60.0 / dm[:, 2])[:, None])[miss]
+    out[miss, 3:6] = dm[miss]
+    # electrons inside the phantom, forward directions (w >= 0.3)
+    ins = kind == 2
+    out[ins, 0] = rng.uniform(-5.0, 5.0, n)[ins]
+    out[ins, 1] = rng.uniform(-5.0, 5.0, n)[ins]
+    out[ins, 2] = rng.uniform(90.0, 110.0, n)[ins]
+    wz = rng.uniform(0.3, 1.0, n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    st = np.sqrt(1.0 - wz * wz)
+    out[ins, 3], out[ins, 4], out[ins, 5] = (st * np.cos(ph))[ins], (st * np.sin(ph))[ins], wz[ins]
+    # energies
+    b = rng.choice(len(w), size=n, p=w)
+    e_ph = edges[b] + rng.uniform(0.0, 1.0, n) * (edges[b + 1] - edges[b])
+    out[:, 6] = np.where(kind == 1, rng.uniform(1.0, 6.0, n), np.where(kind == 2, rng.uniform(0.3, 4.0, n), e_ph))
+    out[:, 7] = np.where((kind == 1) | (kind == 2), 1.0, 0.0)
+    # single precision values, as the engine stores them, with unit directions
+    out = out.astype(np.float32).astype(np.float64)
+    out[:, 3:6] /= np.linalg.norm(out[:, 3:6], axis=1, keepdims=True)
+    return out
+
+
 def response_table_1():
     """The EPID dose-response correction factors k(t, s) the paper measured (Sec. 3.1, Eq. 2,
     Table 1): thickness nodes t (cm of solid water), field-side nodes s (cm), and k[j][i] at
@@ -281,6 +355,17 @@ def response_table_1():
                   [0.995, 0.982, 0.983, 0.996, 0.986],
                   [0.991, 0.997, 1.015, 1.034, 1.043]])
     return t, s, k
+
+
+def lut64_nodes():
+    """Nodes of the large case's 64 x 64 correction table: thickness 0-40 cm and field side
+    2-25 cm, each axis placed so that it contains Table 1's nodes (t = 0, 5, 10, 15, 20 cm;
+    s = 5, 10, 15, 20 cm): t in steps of 0.625 cm up to 38.75 cm, then 40 cm; s in 11 equal
+    steps from 2 to 5 cm and 13 equal steps in each 5 cm interval from 5 to 25 cm."""
+    t = np.concatenate([np.arange(63) * 0.625, [40.0]])
+    s = np.concatenate([2.0 + np.arange(11) * (3.0 / 11.0)] +
+                       [lo + np.arange(13) * (5.0 / 13.0) for lo in (5.0, 10.0, 15.0, 20.0)] + [[25.0]])
+    return t, s
 
 
 # --------------------------------------------------------------------------

@@ -220,3 +220,23 @@ def test_abi_validation_errors(E):
     with pytest.raises(E.EpidmcError) as e:
         eng.set_tally(7, 64, 1 << 20)
     assert e.value.code == -1
+
+
+def test_source_probe_is_the_source_kernels_sampling(E):
+    """The source probe calls the source kernel's own sampling function with the run's key:
+    a probe starting at history h0 and one starting at h0 + 1 agree on history h0 + 1 (the
+    first history is an exact 64-bit id), and for ids below and above 2^32 the energies the
+    probe reports are the incident energies that a diagnostic run of those histories
+    records."""
+    cfg = synth.coupled_hetero_small()
+    eng = E.Engine(0, seed=7).configure(cfg, batches=2, max_chunk=1 << 12, diag=True)
+    eng.bind()
+    for h0 in (34_614_807, (1 << 32) + 5, (3 << 32) + 123_456):
+        a = eng.debug_sample(4, 3, h0)
+        b = eng.debug_sample(4, 2, h0 + 1)
+        assert np.array_equal(a[1:], b)
+        assert np.all(a[:, 7] == 0) and np.all(a[:, 6] > 0)
+        eng.reset()
+        eng.run(2, first=h0)
+        c = eng.counters()
+        assert c["e_in"] == float(a[0, 6]) + float(a[1, 6]), (h0, c["e_in"], a[:2, 6])

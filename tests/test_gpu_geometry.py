@@ -1,0 +1,102 @@
+"""GPU parity at the benchmark's geometry, through the C ABI: the HIP transport against the
+CPU oracle on the coupled workload's 2 mm phantom and 4-layer EPID at the native 0.39 mm
+pixel pitch (a per-pixel z-gate, where the half-pixel step limit in the phosphor binds, and
+the 2%/2 mm gamma gate on 3.12 mm bins against an oracle image at sigma-bar <= 1%), on a
+phase-space-list source, and on a crop of the large case's 1 mm phantom.
+
+The two narrow-field oracle images are written by tests/golden/make_oracle_goldens.py, which
+calls only the oracle; the other oracle images are computed here."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2510_24154_amd import synth
+from tests._stats import gamma_pass, rebin, sigma_bar, z_gate
+
+pytestmark = pytest.mark.gpu
+THREADS = max(1, min(16, os.cpu_count() or 1))
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_24154_amd as E
+    return E
+
+
+def golden(name):
+    d = np.load(os.path.join(GOLDEN, name + ".npz"))
+    return {k: d[k] for k in d.files}
+
+
+def gpu_image(E, cfg, n, seed=1, phsp=None, **kw):
+    kw.setdefault("batches", 64)
+    kw.setdefault("max_chunk", 1 << 24)
+    eng = E.Engine(0, seed=seed).configure(cfg, phsp=phsp, **kw)
+    eng.bind()
+    eng.run(n)
+    m, v = eng.image()
+    return m.cpu().numpy(), v.cpu().numpy(), eng
+
+
+def test_native_pitch_zgate_against_oracle(E):
+    """Full 2 mm phantom, 4-layer EPID, 0.39 mm pixels (s_pix = 0.195 mm binds in the 0.3 mm
+    phosphor), 1 x 1 cm field: per-pixel z-gate of the engine's image against the oracle's
+    (1.6e7 histories, a few hundred deposits per in-field pixel) at native resolution."""
+    g = golden("oracle_narrow_field_native")
+    cfg = synth.narrow_field(field=float(g["field_cm"]), npx=int(g["npx"]))
+    gm, gv, eng = gpu_image(E, cfg, 400_000_000, max_chunk=1 << 26)
+    res = z_gate(gm, gv, g["mean"], g["var"], thr=0.10, k=1)
+    print("native-pitch z-gate", res)
+    assert res["ok"], res
+    assert res["n"] > 500
+
+
+def test_gamma_2pct_2mm_against_oracle(E):
+    """G3: 2%/2 mm global gamma, 10% threshold, reference = the oracle image, both images
+    8 x 8-binned (3.12 mm pixels, near the paper's 2.5 mm scoring grid) where both have
+    sigma-bar <= 1%: at least 99% of the reference pixels pass.  A 3% gain error on the
+    engine's image fails the same gate."""
+    g = golden("oracle_narrow_field_g3")
+    cfg = synth.narrow_field(field=float(g["field_cm"]), npx=int(g["npx"]))
+    gm, gv, _ = gpu_image(E, cfg, 2_000_000_000, max_chunk=1 << 27)
+    k, pitch = 8, 0.039 * 8
+    rm, rv = rebin(g["mean"], k), rebin(g["var"], k)
+    em, ev = rebin(gm, k), rebin(gv, k)
+    sb_ref, sb_eng = sigma_bar(rm, rv), sigma_bar(em, ev)
+    print("G3: sigma-bar oracle", sb_ref, "engine", sb_eng)
+    assert sb_ref <= 0.01 and sb_eng <= 0.01
+    rate = gamma_pass(rm, em, pitch, dd=0.02, dta=0.2, thr=0.10)
+    print("G3 gamma 2%/2 mm pass rate", rate, "over", int((rm >= 0.1 * rm.max()).sum()), "pixels")
+    assert rate >= 0.99, rate
+    assert gamma_pass(rm, em * 1.03, pitch, dd=0.02, dta=0.2, thr=0.10) < 0.99
+
+
+def test_phase_space_source_zgate(E, orc):
+    """Phase-space-list source (photons and electrons entering from above the box, electrons
+    starting inside it, photons that miss it) on the coupled workload's coarse grid: z-gate
+    against the oracle on the same list, per 4 x 4-binned pixel."""
+    cfg = synth.coupled_hetero_small()
+    ps = synth.phase_space_list()
+    print(f"[oracle] phase-space source: 2e6 histories on {THREADS} threads", flush=True)
+    om, ov, *_ = orc.run(cfg, 2_000_000, seed=1001, threads=THREADS, phsp=ps)
+    gm, gv, _ = gpu_image(E, cfg, 60_000_000, phsp=ps, max_chunk=1 << 23)
+    res = z_gate(gm, gv, om, ov, thr=0.10, k=4)
+    print("phase-space z-gate", res)
+    assert res["ok"], res
+
+
+def test_large_phantom_crop_zgate(E, orc):
+    """A crop of the large case's phantom (1 mm voxels: spine, inner lungs, body wall) under a
+    6 x 6 cm field: z-gate against the oracle per 4 x 4-binned pixel of 3.12 mm."""
+    cfg = synth.large_crop()
+    print(f"[oracle] large-phantom crop: 1.5e6 histories on {THREADS} threads", flush=True)
+    om, ov, *_ = orc.run(cfg, 1_500_000, seed=1001, threads=THREADS)
+    gm, gv, _ = gpu_image(E, cfg, 60_000_000, max_chunk=1 << 23)
+    res = z_gate(gm, gv, om, ov, thr=0.10, k=4)
+    print("large-crop z-gate", res)
+    assert res["ok"], res

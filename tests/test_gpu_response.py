@@ -178,19 +178,20 @@ def test_large_case_transport_energy_ledger(E):
 
 
 def test_dose_response_64x64_lut_matches_oracle(E, orc):
-    """The large case's correction table: 64 thickness nodes over 0-40 cm by 64 field-size
-    nodes over 2-25 cm (a smooth seeded k), bilinear and clamped, against the oracle."""
+    """The large case's correction table: Table 1 resampled by the engine onto 64 thickness
+    nodes over 0-40 cm and 64 field-size nodes over 2-25 cm (both containing Table 1's nodes),
+    applied on the device bilinear and clamped, against the oracle evaluating Table 1 itself:
+    the same function, so the same corrected image."""
     import torch
+    t, s, k = golden_table1()
+    t_nodes, s_nodes = synth.lut64_nodes()
+    lut = E.resample_response_table(t, s, k, t_nodes, s_nodes)
     rng = np.random.default_rng(64)
-    t_nodes = np.linspace(0.0, 40.0, 64)
-    s_nodes = np.linspace(2.0, 25.0, 64)
-    T, S = np.meshgrid(t_nodes, s_nodes)
-    k = 1.0 + 0.05 * np.sin(T / 7.0) * np.cos(S / 5.0) + 0.01 * rng.standard_normal((64, 64))
     cfg = synth.kerma_water(npx=64, pitch=0.5)
     eng = engine_for(E, cfg)
     th = rng.uniform(-5.0, 45.0, (64, 64))
     img = rng.uniform(0.0, 2.0, (64, 64))
-    for s in (1.0, 2.0, 9.37, 25.0, 30.0):
-        out = eng.dose_response(torch.as_tensor(img), torch.as_tensor(th), s, t_nodes, s_nodes, k).cpu().numpy()
-        ref = img * orc.response_factor(t_nodes, s_nodes, k, th, s)
-        assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref)), s
+    for sv in (1.0, 2.0, 5.0, 9.37, 20.0, 25.0, 30.0):
+        out = eng.dose_response(torch.as_tensor(img), torch.as_tensor(th), sv, t_nodes, s_nodes, lut).cpu().numpy()
+        ref = img * orc.response_factor(t, s, k, th, sv)
+        assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref)), sv

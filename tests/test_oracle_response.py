@@ -156,3 +156,40 @@ def test_response_factor_bilinear_between_nodes_and_clamped_outside(orc):
     assert orc.response_factor(t, s, k, 10.0, 2.0) == k[0, 2]
     assert orc.response_factor(t, s, k, 10.0, 25.0) == k[-1, 2]
     assert orc.response_factor(t, s, k, 40.0, 2.0) == k[0, -1]
+
+
+def lut64(orc):
+    """The large case's 64 x 64 correction table as the oracle resamples it: Table 1 (bilinear,
+    clamped) at the nodes of synth.lut64_nodes, k[j][i] at (t_i, s_j)."""
+    t, s, k = golden_table1()
+    tn, sn = synth.lut64_nodes()
+    T, S = np.meshgrid(tn, sn)
+    return tn, sn, orc.response_factor(t, s, k, T, S)
+
+
+def test_lut64_reproduces_table1(orc):
+    """Table 1 resampled onto a 64 x 64 grid whose axes contain Table 1's nodes: interpolating
+    the new table at Table 1's 20 nodes returns Table 1, and at any point it returns the
+    bilinear Table 1 (a bilinear interpolant refined on a grid that keeps the old nodes is the
+    same function), including the clamped region beyond t = 20 cm and outside s = 5-20 cm."""
+    t, s, k = golden_table1()
+    tn, sn, K = lut64(orc)
+    assert len(tn) == 64 and len(sn) == 64 and tn[0] == 0.0 and tn[-1] == 40.0 and sn[0] == 2.0 and sn[-1] == 25.0
+    for j in range(len(s)):
+        for i in range(len(t)):
+            assert abs(orc.response_factor(tn, sn, K, t[i], s[j]) - k[j, i]) <= 1e-15
+    rng = np.random.default_rng(5)
+    tt, ss = rng.uniform(-2.0, 42.0, 400), rng.uniform(1.0, 27.0, 400)
+    np.testing.assert_allclose(orc.response_factor(tn, sn, K, tt, ss), orc.response_factor(t, s, k, tt, ss),
+                               rtol=0, atol=1e-14)
+
+
+def test_engine_resampler_matches_oracle(orc):
+    """The engine's host resampler (epidmc_resample_response_table) builds the same 64 x 64
+    table as the oracle; host code only, no device."""
+    import paper_2510_24154_amd as E
+    t, s, k = golden_table1()
+    tn, sn, K = lut64(orc)
+    np.testing.assert_allclose(E.resample_response_table(t, s, k, tn, sn), K, rtol=0, atol=2e-16)
+    with pytest.raises(ValueError):
+        E.resample_response_table(t[::-1], s, k, tn, sn)   # nodes must ascend
