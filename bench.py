@@ -1,15 +1,18 @@
 """Benchmark of the EPID transit Monte Carlo hot path on one MI355X.
 
-Workload (one "step"): the coupled photon-electron configuration -- 1e8 histories
-from a seeded 6 MV-like spectrum through a 256x256x128 phantom of 2 mm voxels (HU
-from seeded water/lung/bone ellipsoids, 3 materials) into a 4-layer EPID with a
-1024x768 image of 0.39 mm pixels, FP32 transport, FP64 tally, 64 variance batches.
-Inputs are resident in HBM before timing; the timed region is K full runs.
+Workload (one "step"): one delivery of a 40-segment IMRT-like field -- seeded MLC
+apertures of 60 leaf pairs with uneven history counts (1e6-5e7, 3e8 in all) from a
+seeded 6 MV-like spectrum through a 256x256x128 phantom of 2 mm voxels (HU from seeded
+water/lung/bone ellipsoids, 3 materials) into a 4-layer EPID with a 1024x768 image of
+0.39 mm pixels, FP32 transport, FP64 tally, 64 variance batches.  `--workload coupled`
+runs the single 10x10 cm open field at 1e8 histories per step instead.  Inputs are
+resident in HBM before timing; the timed region is K full runs.
 
-Prints one JSON line: histories/s (whole job), the extrapolated time to 1% mean
-relative uncertainty, the roofline figure of the dominant kernel (live HIP-event
-durations from the engine's profiling mode), and the oracle timed on host cores
-over a bounded sample of the same workload.
+Prints one JSON line: histories/s (whole job), the time to 1% mean relative uncertainty
+extrapolated by 1/sqrt(N) from one delivery, the roofline figures of the dominant kernel
+(live HIP-event durations from the engine's profiling mode) against the ALU issue rate and
+against the gather, bandwidth and atomic peaks measured on the same GPU by the library's
+probes, and the oracle timed on the host's cores over a bounded sample of the workload.
 """
 from __future__ import annotations
 
@@ -61,8 +64,8 @@ def profiled_traffic(kernel, workload):
     return None, None
 
 
-# workloads: the default benchmark line is "coupled"; the two segmented fields deliver the
-# whole field (history ids [0, total)) in every step
+# workloads: the default benchmark line is "imrt40"; the segmented fields deliver the whole
+# field (history ids [0, total)) in every step
 WORKLOADS = {
     "coupled": ("coupled 6MV-like spectrum, 256x256x128 HU phantom (water/lung/bone), "
                 "4-layer EPID 1024x768 @0.39 mm, 1e8 histories per step", HISTORIES),
@@ -289,12 +292,103 @@ def equal_rmse(rmse, seconds, denoised_rmse, denoised_s):
     return n_eq, n_eq / rate / denoised_s, e_ref2
 
 
+def host_cpu():
+    """The host's CPU facts: nproc, the CPUs this process may run on, the cgroup CPU quota
+    (if any) and the lscpu model name."""
+    import subprocess
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        q = open("/sys/fs/cgroup/cpu.max").read().split()
+        if q and q[0] != "max":
+            info["cgroup_cpus"] = round(int(q[0]) / int(q[1]), 2)
+    except (OSError, ValueError, IndexError):
+        pass
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.startswith("Model name:"):
+                info["model"] = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+# a GPU box gives one GPU's worth of host CPUs to a run (16), whatever nproc reports
+HOST_CPUS_PER_GPU = 16
+
+
+def cpu_baseline(cfg, ns, field_total=None):
+    """The oracle as it stands, timed on the host's cores over a bounded sample of the same
+    workload: every CPU the run may use (at most one GPU's share of the host, 16), then one
+    core over a tenth of the sample.  For a segmented field the sample is spread over the
+    field: eight slices of ids starting at k/8 of its total, so every part of the delivery
+    contributes."""
+    import oracle
+    host = host_cpu()
+    threads = max(1, min(HOST_CPUS_PER_GPU, host["affinity"], int(host.get("cgroup_cpus", 1e9)) or 1))
+    P = oracle.Prepared(cfg, 1001)
+    slices = 8 if field_total else 1
+
+    def timed(n, th):
+        per = n // slices
+        t = time.perf_counter()
+        for k in range(slices):
+            first = (k * field_total) // slices if field_total else 0
+            oracle.run(cfg, per, seed=1001, first=first, threads=th, prepared=P)
+        return per * slices, time.perf_counter() - t
+
+    n_all, t_all = timed(ns, threads)
+    n_one, t_one = timed(max(1000 * slices, ns // 10 // max(1, threads // 8)), 1)
+    where = f"{slices} slices of ids spread over the field" if field_total else f"ids 0..{n_all - 1}"
+    return {"value": round(n_all / t_all, 1), "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_all} histories of the same workload ({where}), {t_all:.1f} s wall on {threads} threads",
+            "value_1core": round(n_one / t_one, 1),
+            "sample_1core": f"{n_one} histories, {t_one:.1f} s on 1 thread",
+            "host": host}
+
+
+def peaks(E, torch, table_bytes):
+    """The memory and atomic peaks of this GPU from the library's probes (epidmc_microbench),
+    each timed with HIP events on torch's stream over 10 launches after one warm-up: a
+    streaming copy of 2 GiB, random 4-byte gathers from a table of the phantom's size (and
+    from 4 MiB and 1 GiB tables), FP64 and int64 atomic adds spread over 8 MiB or aimed at 64
+    hot words."""
+    buf = torch.empty(4 << 30, dtype=torch.uint8, device="cuda")
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    out = {}
+    t = timed(lambda: E.microbench(E.MB_COPY, buf))
+    out["copy_GBps"] = round(buf.numel() / t / 1e9, 1)   # half read, half written
+    threads, per = 256 * 2048, 256
+    bits = max(10, min(31, int(round(__import__("math").log2(max(1, table_bytes) / 4)))))
+    for label, b in (("phantom", bits), ("4MiB", 20), ("1GiB", 28)):
+        t = timed(lambda: E.microbench(E.MB_GATHER, buf, b, per, threads))
+        out[f"gather_{label}_Gps"] = round(threads * per / t / 1e9, 2)
+    out["gather_phantom_table_bytes"] = 4 << bits
+    for kind, name in ((E.MB_ATOMIC_F64, "f64"), (E.MB_ATOMIC_I64, "i64")):
+        t = timed(lambda: E.microbench(kind, buf, 20, 64, threads))
+        out[f"atomic_{name}_spread_Gps"] = round(threads * 64 / t / 1e9, 3)
+        t = timed(lambda: E.microbench(kind, buf, 6, 4, threads), reps=3)
+        out[f"atomic_{name}_hot64_Gps"] = round(threads * 4 / t / 1e9, 3)
+    del buf
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=list(WORKLOADS), default="coupled")
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="imrt40")
     ap.add_argument("--histories", type=int, default=None,
                     help="histories per step (default: the workload's; a segmented field is rescaled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -427,6 +521,23 @@ def main():
                 "thickness_cm_range": [round(float(th.min()), 3), round(float(th.max()), 3)],
                 "corrected_over_plain": round(float(corrected.sum() / img.sum()), 5)}
 
+    # on-box peaks, then the dominant kernel's rates as fractions of them: voxel gathers per
+    # second against random 4-byte gathers from a table of the phantom's size, its calibrated
+    # memory traffic against the streaming copy, and the image tally's atomic adds per second
+    # of the step against spread FP64 atomics
+    pk = peaks(E, torch, int(np.prod(cfg["phantom"]["shape"])) * 4)
+    t_step = dt / a.steps
+    gathers_ps = units[dom] / launches / avg_s if dom in (0, 1) and avg_s > 0 else None
+    fractions = {
+        "alu": roof["frac"],
+        "gather": round(gathers_ps / (pk["gather_phantom_Gps"] * 1e9), 4) if gathers_ps else None,
+        "hbm": round(roof["traffic_GBps"] / pk["copy_GBps"], 4) if roof["traffic_GBps"] else None,
+        "atomic": round(c["tally_deposits"] / (t_step if segmented else dt) / (pk["atomic_f64_spread_Gps"] * 1e9), 6),
+    }
+    fractions["binding"] = max((k for k in ("alu", "gather", "hbm", "atomic") if fractions[k] is not None),
+                               key=lambda k: fractions[k])
+    roof["gathers_per_s"] = round(gathers_ps, 1) if gathers_ps else None
+
     measured = None
     if a.t1_measured and segmented:
         print("--t1-measured runs on the coupled workload only (a field's ids end at its total)", file=sys.stderr)
@@ -460,25 +571,12 @@ def main():
         torch.cuda.synchronize()
 
     cpu = None
-    if not a.no_cpu_baseline and a.workload == "coupled":
-        import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
-        ns = a.cpu_sample
-        tc = time.perf_counter()
-        oracle.run(cfg, ns, seed=1001, first=0, threads=threads)
-        tcd = time.perf_counter() - tc
-        # the same oracle on one core, over a tenth of the sample
-        n1 = max(1000, ns // 10 // max(1, threads // 8))
-        t1c = time.perf_counter()
-        oracle.run(cfg, n1, seed=1001, first=0, threads=1)
-        t1d = time.perf_counter() - t1c
-        cpu = {"value": round(ns / tcd, 1), "unit": "histories/s", "cores": threads, "kind": "oracle",
-               "sample": f"{ns} histories of the same workload (ids 0..{ns - 1}), {tcd:.1f} s wall on {threads} threads",
-               "value_1core": round(n1 / t1d, 1),
-               "sample_1core": f"{n1} histories (ids 0..{n1 - 1}), {t1d:.1f} s on 1 thread"}
+    if not a.no_cpu_baseline and a.workload in ("coupled", "imrt40"):
+        cpu = cpu_baseline(cfg, a.cpu_sample, n_default if segmented else None)
+        print(f"[cpu_baseline] {cpu}", file=sys.stderr, flush=True)
 
     out = {
-        "metric": "photon histories/s (coupled transport to a 1% EPID image)",
+        "metric": "photon histories/s and s-to-1%-uncertainty EPID image; denoised vs plain at \u226599% gamma",
         "value": round(value, 1),
         "unit": "histories/s",
         "n_gpus": 1,
@@ -493,12 +591,14 @@ def main():
         "config": {"workload": desc, "name": a.workload,
                    "histories_per_step": n_step, "batches": BATCHES, "tally": "fp64",
                    "first_history": first, "chunk": min(chunk, n_step), "autotune": tuned},
-        "s_to_1pct_extrapolated": round(t1_s, 2) if t1_s else None,
-        "s_to_1pct_extrapolated_raw_selection": round(t1, 2) if t1 else None,
+        "s_to_1pct_extrapolated": round(t1, 2) if t1 else None,
+        "s_to_1pct_extrapolated_smoothed_selection": round(t1_s, 2) if t1_s else None,
         "sigma_bar_smoothed_selection": round(sb_s, 5),
         "sigma_bar_at_N": round(sb, 5),
         "N_for_sigma_bar": n_step if segmented else n,
         "roofline": roof,
+        "roofline_fractions": fractions,
+        "peaks": pk,
         "cpu_baseline": cpu,
         "dose_response": response,
         "t1pct_measured": measured,

@@ -296,6 +296,20 @@ epidmc_status epidmc_debug_records(epidmc_ctx *c, uint32_t *dev_pix, float *dev_
 epidmc_status epidmc_debug_table(epidmc_ctx *c, int kind, int index, const float *dev_E, float *dev_out,
                                  uint64_t n, void *stream);
 
+/* ---- measurement probes (no part of the transport) ----------------------------- */
+/* Kernels that measure the peaks the transport kernels' rates are compared with, on the GPU
+ * that runs them.  dev_buf: caller-owned device memory of `bytes` bytes, contents
+ * overwritten.  kind 0: streaming copy of the first half of dev_buf into the second half
+ * (16-byte words; the other arguments are ignored).  kind 1: `threads` threads (a multiple of
+ * 256) each make ops_per_thread 4-byte loads at pseudo-random indices of a table of
+ * 2^log2_elems words at the start of dev_buf.  kind 2 / 3: the same pattern of FP64 / int64
+ * atomic adds (no returned value) into a table of 2^log2_elems 8-byte words, log2_elems 6
+ * concentrating them on 64 hot words.  Asynchronous on `stream`; the caller times it.
+ * EPIDMC_E_ARG for a bad kind, thread count or log2_elems outside 1..31; EPIDMC_E_WORKSPACE
+ * when the table does not fit in `bytes`. */
+epidmc_status epidmc_microbench(int kind, void *dev_buf, size_t bytes, int log2_elems, uint32_t ops_per_thread,
+                                uint32_t threads, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

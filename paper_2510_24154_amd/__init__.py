@@ -83,6 +83,7 @@ EXPORTS = [
     "epidmc_radiological_thickness", "epidmc_field_size", "epidmc_dose_response",
     "epidmc_resample_response_table",
     "epidmc_debug_philox", "epidmc_debug_sample", "epidmc_debug_table", "epidmc_debug_records",
+    "epidmc_microbench",
 ] + DN_EXPORTS
 
 _lib = None
@@ -127,6 +128,7 @@ def load_library(path: str = LIB_PATH):
         "epidmc_debug_sample": [vp, i32, f64, f64, f64, vp, u64, vp],
         "epidmc_debug_table": [vp, i32, i32, vp, vp, u64, vp],
         "epidmc_debug_records": [vp, vp, vp, u64, ct.POINTER(u64), vp],
+        "epidmc_microbench": [i32, vp, ct.c_size_t, i32, u32, u32, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -393,3 +395,18 @@ def resample_response_table(t_nodes, s_nodes, k, t_out, s_out):
     if st != 0:
         raise ValueError(f"epidmc_resample_response_table failed: status {st}")
     return out
+
+
+MB_COPY, MB_GATHER, MB_ATOMIC_F64, MB_ATOMIC_I64 = 0, 1, 2, 3
+
+
+def microbench(kind, buf, log2_elems=0, ops_per_thread=0, threads=0):
+    """Launch one measurement probe (epidmc_microbench) on torch's current stream over the
+    device tensor `buf` (its bytes are overwritten); the caller times it."""
+    import torch
+    L = load_library()
+    rc = L.epidmc_microbench(int(kind), ct.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                             int(log2_elems), int(ops_per_thread), int(threads),
+                             ct.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise EpidmcError(rc, "epidmc_microbench")

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libepidmc.so")
-SOURCES = ["epidmc.cpp", "tables.cpp", "kernels.hip", "unet.hip"]
+SOURCES = ["epidmc.cpp", "tables.cpp", "kernels.hip", "unet.hip", "microbench.hip"]
 # FP32 division and square root at the hardware's 1-2.5 ulp instead of correctly rounded
 # sequences, and FP32 denormals flushed: no FP32 quantity of the transport comes near the
 # denormal range, and the tallies and positions that need more than FP32 are FP64
