@@ -63,6 +63,20 @@ epidmc_status epidmc_dn_wgrad(const uint16_t *x, int ldx, int c_in, const uint16
                               int n, int h, int w_px, int k, float *dw, float *db,
                               float *scratch, size_t scratch_floats, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): epidmc_dn_wgrad with the partial sums in
+ * a scratch array that the library holds in device memory, one per GPU it runs on, until the
+ * process ends; nothing is allocated or freed by the call.  Same arguments, kernels and
+ * result as epidmc_dn_wgrad (bit for bit); returns EPIDMC_E_WORKSPACE when the shape needs
+ * more than EPIDMC_DN_WGRAD_NOALLOC_FLOATS floats of scratch (epidmc_dn_wgrad_scratch gives
+ * the need).  Every call on one GPU uses that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from different threads) race and must be serialised by the
+ * caller.  The first call on a device resolves the array's address on the current device. */
+#define EPIDMC_DN_WGRAD_NOALLOC_FLOATS (10u << 20) /* 40 MiB: every layer of the U-Net below for
+                                                  * batches of up to 8 images of 1024 x 768 */
+epidmc_status epidmc_dn_wgrad_noalloc(const uint16_t *x, int ldx, int c_in, const uint16_t *g, int ldg, int c_out,
+                                      int n, int h, int w_px, int k, float *dw, float *db, void *stream);
+
 /* BF16 copies of FP32 weights w [c_out][k][k][c_in]: w_fwd in the same layout, and w_bwd
  * [c_in][k][k][c_out] with the taps reversed (w_bwd[c][i][j][o] = w[o][k-1-i][k-1-j][c]),
  * the weights of the backward-data convolution.  Either output may be NULL. */

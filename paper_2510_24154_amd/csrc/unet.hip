@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1121,6 +1122,48 @@ epidmc_status epidmc_dn_wgrad(const uint16_t *x, int ldx, int c_in, const uint16
     if (!x || !g || !dw || !scratch || (long long)n * h * w_px == 0) return EPIDMC_E_ARG;
     if (scratch_floats < wgrad_plan((long long)n * h * w_px, k, c_in, c_out).floats) return EPIDMC_E_WORKSPACE;
     return launch_wgrad(x, ldx, c_in, g, ldg, c_out, n, h, w_px, k, dw, db, scratch, (hipStream_t)stream) == hipSuccess
+               ? EPIDMC_OK
+               : EPIDMC_E_DEVICE;
+}
+
+// Scratch of the allocation-free weight gradient: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never uses the array's name
+// as an address: the device address comes from hipGetSymbolAddress, once per device, with
+// that device current.
+static __device__ __align__(256) float scratch[EPIDMC_DN_WGRAD_NOALLOC_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+float *scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+static epidmc_status noalloc_scratch(float **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return EPIDMC_E_DEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return EPIDMC_E_DEVICE;
+        scratch_ptr[dev] = (float *)p;
+    }
+    *out = scratch_ptr[dev];
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_dn_wgrad_noalloc(const uint16_t *x, int ldx, int c_in, const uint16_t *g, int ldg, int c_out,
+                                      int n, int h, int w_px, int k, float *dw, float *db, void *stream)
+{
+    epidmc_status st = conv_shape_ok(ldx, c_in, ldg, c_out, n, h, w_px, k);
+    if (st != EPIDMC_OK) return st;
+    if (!x || !g || !dw || (long long)n * h * w_px == 0) return EPIDMC_E_ARG;
+    if (wgrad_plan((long long)n * h * w_px, k, c_in, c_out).floats > (size_t)EPIDMC_DN_WGRAD_NOALLOC_FLOATS)
+        return EPIDMC_E_WORKSPACE;
+    float *ws = nullptr;
+    st = noalloc_scratch(&ws);
+    if (st != EPIDMC_OK) return st;
+    return launch_wgrad(x, ldx, c_in, g, ldg, c_out, n, h, w_px, k, dw, db, ws, (hipStream_t)stream) == hipSuccess
                ? EPIDMC_OK
                : EPIDMC_E_DEVICE;
 }

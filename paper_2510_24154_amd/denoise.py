@@ -10,7 +10,8 @@ import ctypes as ct
 import numpy as np
 
 DN_EXPORTS = [
-    "epidmc_dn_conv", "epidmc_dn_wgrad_scratch", "epidmc_dn_wgrad", "epidmc_dn_weights", "epidmc_dn_pool",
+    "epidmc_dn_conv", "epidmc_dn_wgrad_scratch", "epidmc_dn_wgrad", "epidmc_dn_wgrad_noalloc",
+    "epidmc_dn_weights", "epidmc_dn_pool",
     "epidmc_dn_upsample", "epidmc_dn_upsample_backward", "epidmc_dn_skip_backward",
     "epidmc_unet_create", "epidmc_unet_destroy", "epidmc_unet_last_error", "epidmc_unet_param_count",
     "epidmc_unet_layer", "epidmc_unet_layers", "epidmc_unet_workspace_size", "epidmc_unet_bind",
@@ -26,6 +27,7 @@ def declare(L):
         "epidmc_dn_conv": [vp, i32, i32, vp, vp, vp, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp],
         "epidmc_dn_wgrad_scratch": [i32, i32, i32, i32, i32, i32, ct.POINTER(sz)],
         "epidmc_dn_wgrad": [vp, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp],
+        "epidmc_dn_wgrad_noalloc": [vp, i32, i32, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp],
         "epidmc_dn_weights": [vp, i32, i32, i32, vp, vp, vp],
         "epidmc_dn_pool": [vp, i32, vp, i32, i32, i32, i32, i32, vp],
         "epidmc_dn_upsample": [vp, i32, vp, i32, i32, i32, i32, i32, vp],
@@ -105,6 +107,26 @@ def wgrad(x, g, k, with_bias=True):
     _check(_lib().epidmc_dn_wgrad(_p(x), _ld(x), ci, _p(g), _ld(g), co, n, h, wd, k, _p(dw), _p(db), _p(scratch),
                                   fl.value, _stream(torch)), "epidmc_dn_wgrad")
     return dw, db
+
+
+# floats of the library-held scratch of epidmc_dn_wgrad_noalloc (EPIDMC_DN_WGRAD_NOALLOC_FLOATS)
+WGRAD_NOALLOC_FLOATS = 10 << 20
+
+
+def wgrad_noalloc(x, g, k, with_bias=True, dw=None, db=None):
+    """epidmc_dn_wgrad with the library's own scratch (the call allocates nothing; dw and db
+    are allocated here unless given)."""
+    import torch
+    n, h, wd, ci = x.shape
+    co = g.shape[3]
+    if dw is None:
+        dw = torch.empty((co, k, k, ci), dtype=torch.float32, device=x.device)
+    if db is None and with_bias:
+        db = torch.empty(co, dtype=torch.float32, device=x.device)
+    _check(_lib().epidmc_dn_wgrad_noalloc(_p(x), _ld(x), ci, _p(g), _ld(g), co, n, h, wd, k, _p(dw),
+                                          _p(db) if with_bias else None, _stream(torch)),
+           "epidmc_dn_wgrad_noalloc")
+    return dw, (db if with_bias else None)
 
 
 def weights(w_f32, backward=True):
