@@ -203,6 +203,27 @@ epidmc_status epidmc_set_diagnostics(epidmc_ctx *c, int enable);
  * runs on and the durations are summed into epidmc_counters.kernel_ms. */
 epidmc_status epidmc_set_profiling(epidmc_ctx *c, int enable);
 
+/* Queue passes (the regrouping of Sec. 2.1's transport into per-kind work queues): the first
+ * `device_passes` passes of each chunk of histories are launched without waiting for the host
+ * (every particle kind at its resident grid size, blocks beyond the queue's need leaving at
+ * once on the device); the host reads the queues back once after them and drives any further
+ * passes itself.  -1 (the default): as many device-driven passes as the previous chunk had
+ * non-empty ones; 0: host-driven throughout.  Grids are sized for about `items_per_lane`
+ * queued particles per lane (default 2).  Neither changes any trajectory: a fixed-point image
+ * is the same bit for bit for every setting.  EPIDMC_E_ARG outside [-1, 24] and [1, 64]. */
+epidmc_status epidmc_set_passes(epidmc_ctx *c, int device_passes, int items_per_lane);
+/* Graph runs (the batched delivery of a whole IMRT field, Sec. 2.3: all segments of a run in
+ * one launch): when enabled, a run call for a history range captures the whole run -- every
+ * chunk's source and `passes` device-driven queue passes (0: the previous chunk's non-empty
+ * passes plus two, or 12 before any chunk ran), and the folds -- as one HIP graph on a stream
+ * of the library's own, and replays it on `stream`; a later call with the same history range
+ * replays the graph (the same histories again: the tally adds them once more).  A run whose
+ * queues still hold particles after the captured passes returns EPIDMC_E_OVERFLOW (its tally
+ * is then incomplete: reset it and raise `passes`).  Needs the FP64 or fixed-point tally and
+ * diagnostics off (EPIDMC_E_ARG otherwise); profiling events are not recorded in graph runs.
+ * Any set_* call or a new workspace drops the captured graph. */
+epidmc_status epidmc_set_graph(epidmc_ctx *c, int enable, int passes);
+
 /* ---- memory ------------------------------------------------------------------ */
 epidmc_status epidmc_workspace_size(epidmc_ctx *c, size_t *bytes);
 /* Bind caller-owned device memory (256-byte aligned, >= workspace_size bytes) and

@@ -77,7 +77,7 @@ EXPORTS = [
     "epidmc_create", "epidmc_destroy", "epidmc_last_error", "epidmc_set_materials", "epidmc_set_physics",
     "epidmc_set_phantom_hu", "epidmc_set_phantom_direct", "epidmc_set_epid", "epidmc_set_source_spectrum",
     "epidmc_set_source_phsp", "epidmc_set_segments", "epidmc_set_tally", "epidmc_set_diagnostics",
-    "epidmc_set_profiling",
+    "epidmc_set_profiling", "epidmc_set_passes", "epidmc_set_graph",
     "epidmc_workspace_size", "epidmc_bind_workspace", "epidmc_run", "epidmc_run_until", "epidmc_read_image",
     "epidmc_sigma_bar", "epidmc_reset_tally", "epidmc_get_counters",
     "epidmc_radiological_thickness", "epidmc_field_size", "epidmc_dose_response",
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH):
         "epidmc_set_tally": [vp, i32, i32, u64],
         "epidmc_set_diagnostics": [vp, i32],
         "epidmc_set_profiling": [vp, i32],
+        "epidmc_set_passes": [vp, i32, i32],
+        "epidmc_set_graph": [vp, i32, i32],
         "epidmc_workspace_size": [vp, ct.POINTER(ct.c_size_t)],
         "epidmc_bind_workspace": [vp, vp, ct.c_size_t, vp],
         "epidmc_run": [vp, u64, u64, vp],
@@ -246,6 +248,12 @@ class Engine:
 
     def set_profiling(self, on=True):
         self._check(self.L.epidmc_set_profiling(self.h, 1 if on else 0))
+
+    def set_passes(self, device_passes=-1, items_per_lane=2):
+        self._check(self.L.epidmc_set_passes(self.h, int(device_passes), int(items_per_lane)))
+
+    def set_graph(self, on=True, passes=0):
+        self._check(self.L.epidmc_set_graph(self.h, 1 if on else 0, int(passes)))
 
     def configure(self, cfg, tally=TALLY_FP64, batches=64, max_chunk=1 << 21, diag=False, phsp=None):
         """Apply a workload description (see paper_2510_24154_amd.synth)."""

@@ -130,6 +130,11 @@ struct Params {
     unsigned long long h0, h1;  // history ids [h0, h1)
     unsigned long long run_first, run_n;
     int run_batches, ring;      // batch of history h = (h-run_first)*run_batches/run_n; slot = batch % ring
+    // device-driven passes: the kinds are launched at their resident grid size whatever their
+    // queues hold, and each block first compares its index with the blocks the pass-start
+    // kernel's total calls for (about ipl items per lane); 0: the host sized the grid
+    int gated;
+    int ipl;                    // items per lane the grids are sized for
 
     // tally
     int tally_mode;

@@ -26,7 +26,7 @@ hipError_t launch_sigma_bar(const Params &P, double n, double nb, double thr, do
 hipError_t launch_diag_check(const Params &P, uint32_t nh, unsigned long long *maxbits, double *sums, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_pass_start(const Params &P, const uint32_t *cnt, uint32_t *tot, uint32_t *fills, uint32_t *heads,
-                             size_t words, hipStream_t s);
+                             size_t words, hipStream_t s, uint32_t *hist);
 hipError_t launch_radthick(const RadArgs &A, hipStream_t s);
 hipError_t launch_response(const RespArgs &A, hipStream_t s);
 hipError_t launch_dbg_philox(const Params &P, const uint32_t *ctr, uint32_t *out, unsigned long long n, hipStream_t s);
@@ -62,7 +62,11 @@ constexpr size_t CTL_ERR = 64;                // u32
 constexpr size_t CTL_STATS = 128;             // S_NSTAT u64
 constexpr size_t CTL_DIAG = CTL_STATS + 8 * 32;   // max-residual bits, e_in, e_ledger
 constexpr size_t CTL_SIGMA = CTL_DIAG + 64;   // double
-constexpr size_t CTL_BYTES = 1024;
+constexpr int MAX_DEV_PASSES = 24;            // device-driven passes per chunk (at most)
+constexpr int MAX_GRAPH_CHUNKS = 32;          // chunks of one captured run (at most)
+constexpr size_t CTL_PASSHIST = 512;          // [MAX_DEV_PASSES][NQ + 1] u32: per-pass totals and error word
+constexpr size_t CTL_LEFT = 1024;             // [MAX_GRAPH_CHUNKS][NQ + 1] u32: totals after a captured chunk's last pass
+constexpr size_t CTL_BYTES = CTL_LEFT + (size_t)MAX_GRAPH_CHUNKS * (NQ + 1) * 4;
 
 }  // namespace
 
@@ -120,6 +124,24 @@ struct epidmc_ctx {
     double kernel_ms[NQ] = {0, 0, 0, 0};
     uint64_t kernel_launches[NQ] = {0, 0, 0, 0};
     uint32_t last_nrec = 0;         // Kahan mode: records of the last chunk
+    // passes: the first `dev_passes` passes of a chunk are launched without a host round trip
+    // (-1: as many as the previous chunk had non-empty passes); grids for about `ipl` items
+    // per lane
+    int dev_passes = -1, last_passes = 0, ipl = ITEMS_PER_LANE;
+    hipEvent_t dev_ev[MAX_DEV_PASSES][2][NQ] = {};
+    // the previous chunk's queue totals per pass (zero where a queue was empty or the pass did
+    // not run), from which device-driven passes size their grids
+    uint32_t prev_rows[MAX_DEV_PASSES][NQ] = {};
+    bool have_rows = false;
+    // a whole run captured as one graph (FP64 or fixed-point tally, diagnostics off), replayed
+    // while the run's history range is the same
+    int graph = 0, graph_passes = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t gx = nullptr;
+    uint64_t g_first = 0, g_n = 0;
+    int g_chunks = 0, g_passes = 0;
+    hipStream_t cap = nullptr;      // the stream a run is captured on (capture needs a stream other than the null stream)
+    uint64_t graph_launches = 0;
     // accumulated
     double n_total = 0, b_total = 0;
     uint64_t launches = 0, queue_peak = 0;
@@ -140,7 +162,14 @@ static epidmc_status fail(epidmc_ctx *c, epidmc_status s, const std::string &m)
 
 static bool finite3(const float v[3]) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
-static void unbind(epidmc_ctx *c) { c->bound = false; }
+static void drop_graph(epidmc_ctx *c);
+
+// a change of the model invalidates the workspace and any captured run
+static void unbind(epidmc_ctx *c)
+{
+    c->bound = false;
+    drop_graph(c);
+}
 
 extern "C" {
 
@@ -176,6 +205,13 @@ epidmc_status epidmc_destroy(epidmc_ctx *c)
         if (c->ks[k]) (void)hipStreamDestroy(c->ks[k]);
     }
     if (c->go) (void)hipEventDestroy(c->go);
+    for (int p = 0; p < MAX_DEV_PASSES; ++p)
+        for (int b = 0; b < 2; ++b)
+            for (int k = 0; k < NQ; ++k)
+                if (c->dev_ev[p][b][k]) (void)hipEventDestroy(c->dev_ev[p][b][k]);
+    if (c->gx) (void)hipGraphExecDestroy(c->gx);
+    if (c->g) (void)hipGraphDestroy(c->g);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->host) (void)hipHostFree(c->host);
     delete c;
     return EPIDMC_OK;
@@ -428,8 +464,33 @@ epidmc_status epidmc_set_profiling(epidmc_ctx *c, int enable)
         HIPCHK(hipSetDevice(c->device));
         for (int b = 0; b < 2; ++b)
             for (int k = 0; k < NQ; ++k) HIPCHK(hipEventCreate(&c->ev[b][k]));
+        for (int p = 0; p < MAX_DEV_PASSES; ++p)
+            for (int b = 0; b < 2; ++b)
+                for (int k = 0; k < NQ; ++k) HIPCHK(hipEventCreate(&c->dev_ev[p][b][k]));
     }
     c->prof = enable ? 1 : 0;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_passes(epidmc_ctx *c, int device_passes, int items_per_lane)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(device_passes >= -1 && device_passes <= MAX_DEV_PASSES, EPIDMC_E_ARG, "device passes in [-1, 24]");
+    REQUIRE(items_per_lane >= 1 && items_per_lane <= 64, EPIDMC_E_ARG, "items per lane in [1, 64]");
+    c->dev_passes = device_passes;
+    c->ipl = items_per_lane;
+    return EPIDMC_OK;
+}
+
+epidmc_status epidmc_set_graph(epidmc_ctx *c, int enable, int passes)
+{
+    if (!c) return EPIDMC_E_ARG;
+    REQUIRE(passes >= 0 && passes <= MAX_DEV_PASSES, EPIDMC_E_ARG, "graph passes in [0, 24]");
+    REQUIRE(!enable || (c->tally_mode != 2 && !c->diag), EPIDMC_E_ARG,
+            "graph runs need the FP64 or fixed-point tally and diagnostics off");
+    drop_graph(c);
+    c->graph = enable ? 1 : 0;
+    c->graph_passes = passes;
     return EPIDMC_OK;
 }
 
@@ -555,6 +616,9 @@ extern "C" epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev, size_t 
     const Layout L = make_layout(c);
     REQUIRE(bytes >= L.total, EPIDMC_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
     HIPCHK(hipSetDevice(c->device));
+    drop_graph(c);   // a captured run holds the previous workspace's addresses
+    c->have_rows = false;   // pass statistics of another model
+    c->last_passes = 0;
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)dev;
 
@@ -817,7 +881,37 @@ static epidmc_status kind_streams(epidmc_ctx *c)
     return EPIDMC_OK;
 }
 
-static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStream_t s)
+// Launch one pass's kernels: each kind on its own stream (the last on the run stream), all
+// starting together once the pass-start kernel has run, the run stream waiting for the others
+// afterwards.  `blocks[k] == 0` skips a kind; `ev` (or null) brackets each launch for profiling.
+static epidmc_status launch_pass(epidmc_ctx *c, const Params &P, const unsigned *blocks, hipEvent_t (*ev)[NQ],
+                                 hipStream_t s)
+{
+    HIPCHK(hipEventRecord(c->go, s));
+    for (int k = 0; k < NQ; ++k) {
+        if (!blocks[k]) continue;
+        const bool own = k < NQ - 1;
+        hipStream_t ks = own ? c->ks[k] : s;
+        if (own) HIPCHK(hipStreamWaitEvent(ks, c->go, 0));
+        if (ev) HIPCHK(hipEventRecord(ev[0][k], ks));
+        HIPCHK(launch_transport(k, P, blocks[k], ks));
+        if (ev) HIPCHK(hipEventRecord(ev[1][k], ks));
+        if (own) HIPCHK(hipEventRecord(c->done[k], ks));
+    }
+    for (int k = 0; k < NQ - 1; ++k)
+        if (blocks[k]) HIPCHK(hipStreamWaitEvent(s, c->done[k], 0));
+    return EPIDMC_OK;
+}
+
+// One chunk of histories [h0, h1): the source, then queue passes until every queue is empty.
+// The first K passes are device-driven: every kind is launched at its resident grid size and
+// its blocks beyond the queue's need leave at once (gated_off), so no pass waits for the host;
+// the pass-start kernel keeps each pass's totals, which the host reads once afterwards.  The
+// passes after that are host-driven (one readback each, grids sized from the totals).  In a
+// graph capture (`capture`) the chunk runs exactly K device-driven passes and a last
+// pass-start kernel that flags any queue still holding particles.
+static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStream_t s, bool capture = false,
+                               int chunk = 0)
 {
     {
         const epidmc_status st = kind_streams(c);
@@ -826,6 +920,8 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
     Params P = c->P;
     P.h0 = h0;
     P.h1 = h1;
+    P.ipl = c->ipl;
+    P.gated = 0;
     // history ids of 2^32 and above: the counter's history word holds the low 32 bits and
     // the high word selects the key (odd multipliers keep distinct high words distinct);
     // a chunk never spans a 2^32 boundary, so one key serves the whole chunk
@@ -834,6 +930,7 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
     P.key1 ^= hi * 0x85EBCA6Bu;
     uint32_t *cnt = P.cnt;
     uint32_t *seg = (uint32_t *)(c->ws + c->lay.segc.off);   // [set A, set B, heads][NQ][NSEG] x CSTRIDE
+    uint32_t *hist = (uint32_t *)(c->ws + c->lay.ctl.off + CTL_PASSHIST);
     HIPCHK(launch_zero(cnt, 64, s));
     HIPCHK(launch_zero(seg, 3 * SEG_SET * 4, s));
     // the source appends into buffer set 0
@@ -847,14 +944,71 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
     HIPCHK(launch_source(P, s));
     ++c->launches;
     int cur = 0;
+    const int K = std::min(capture ? c->graph_passes : (c->dev_passes < 0 ? c->last_passes : c->dev_passes),
+                           MAX_DEV_PASSES);
+    const bool prof = c->prof && !capture;
+    int pass = 0;
+    // device-driven passes: pass-start (totals kept per pass), then every kind, gated on the device
+    for (; pass < K; ++pass) {
+        HIPCHK(launch_pass_start(P, seg + cur * SEG_SET, cnt, seg + (1 - cur) * SEG_SET, seg + 2 * SEG_SET, SEG_SET, s,
+                                 hist + pass * (NQ + 1)));
+        use(cur);
+        P.gated = 1;
+        // grids sized from the previous chunk's totals of the same pass, with headroom (a queue
+        // that holds more than its grid was sized for is still drained, by fewer waves); a kind
+        // that was empty gets one workgroup, which leaves at once when its queue is empty again
+        unsigned blocks[NQ];
+        for (int k = 0; k < NQ; ++k) {
+            const uint64_t full = (uint64_t)c->n_cu * c->occ[k], per = (uint64_t)WG * c->ipl;
+            const uint64_t want = c->have_rows ? (c->prev_rows[pass][k] + c->prev_rows[pass][k] / 4 + per - 1) / per : full;
+            blocks[k] = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, full));
+        }
+        const epidmc_status st = launch_pass(c, P, blocks, prof ? c->dev_ev[pass] : nullptr, s);
+        if (st != EPIDMC_OK) return st;
+        P.gated = 0;
+        cur = 1 - cur;
+    }
+    if (capture) {
+        // what the queues still hold after the last captured pass, kept per chunk: the host
+        // checks after the replay that every queue was empty
+        HIPCHK(launch_pass_start(P, seg + cur * SEG_SET, cnt, seg + (1 - cur) * SEG_SET, seg + 2 * SEG_SET, SEG_SET, s,
+                                 (uint32_t *)(c->ws + c->lay.ctl.off + CTL_LEFT) + chunk * (NQ + 1)));
+        return EPIDMC_OK;
+    }
     bool timed[NQ] = {false, false, false, false};
-    for (int pass = 0; pass < 100000; ++pass) {
+    int nonempty = -1;   // the first pass that found every queue empty
+    uint32_t rows[MAX_DEV_PASSES][NQ] = {};
+    for (; pass < 100000; ++pass) {
         // the input set's totals and the error word in one readback; the kernel also clears
         // the other set's fill counters and the consume heads for this pass (the previous
         // pass, which used them, has ended: the run stream waited for it)
-        HIPCHK(launch_pass_start(P, seg + cur * SEG_SET, cnt, seg + (1 - cur) * SEG_SET, seg + 2 * SEG_SET, SEG_SET, s));
+        HIPCHK(launch_pass_start(P, seg + cur * SEG_SET, cnt, seg + (1 - cur) * SEG_SET, seg + 2 * SEG_SET, SEG_SET, s,
+                                 nullptr));
         HIPCHK(hipMemcpyAsync(c->host, cnt, (NQ + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (pass == K && K > 0)
+            HIPCHK(hipMemcpyAsync(c->host + 16, hist, (size_t)K * (NQ + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (pass == K && K > 0) {
+            // what the device-driven passes held, and their profiled kernels
+            for (int p = 0; p < K; ++p) {
+                const uint32_t *row = c->host + 16 + p * (NQ + 1);
+                bool any = false;
+                for (int k = 0; k < NQ; ++k) {
+                    rows[p][k] = row[k];
+                    if (!row[k]) continue;
+                    any = true;
+                    ++c->launches;
+                    c->queue_peak = std::max<uint64_t>(c->queue_peak, row[k]);
+                    if (prof) {
+                        float ms = 0.0f;
+                        HIPCHK(hipEventElapsedTime(&ms, c->dev_ev[p][0][k], c->dev_ev[p][1][k]));
+                        c->kernel_ms[k] += ms;
+                        ++c->kernel_launches[k];
+                    }
+                }
+                if (!any && nonempty < 0) nonempty = p;
+            }
+        }
         for (int k = 0; k < NQ; ++k)
             if (timed[k]) {
                 float ms = 0.0f;
@@ -865,39 +1019,35 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
             }
         uint32_t n[NQ];
         std::memcpy(n, c->host, sizeof n);
+        if (pass < MAX_DEV_PASSES) std::memcpy(rows[pass], n, sizeof n);
         if (c->host[NQ] & (ERR_QUEUE | ERR_NAN | ERR_STEPS | ERR_SAMPLE)) return check_error_word(c, c->host[NQ]);
         bool any = false;
         for (int k = 0; k < NQ; ++k) {
             any |= n[k] > 0;
             c->queue_peak = std::max<uint64_t>(c->queue_peak, n[k]);
         }
-        if (!any) break;
-        use(cur);
-        // the pass's kernels start together once the counters are cleared, each on its
-        // kind's stream (the last kind on the run stream); the run stream then waits for
-        // the others before the next pass
-        HIPCHK(hipEventRecord(c->go, s));
-        for (int k = 0; k < NQ; ++k) {
-            if (!n[k]) continue;
-            const uint64_t per_block = (uint64_t)WG * ITEMS_PER_LANE;
-            const uint64_t want = (n[k] + per_block - 1) / per_block;
-            const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * c->occ[k]));
-            const bool own = k < NQ - 1;
-            hipStream_t ks = own ? c->ks[k] : s;
-            if (own) HIPCHK(hipStreamWaitEvent(ks, c->go, 0));
-            if (c->prof) HIPCHK(hipEventRecord(c->ev[0][k], ks));
-            HIPCHK(launch_transport(k, P, blocks, ks));
-            if (c->prof) {
-                HIPCHK(hipEventRecord(c->ev[1][k], ks));
-                timed[k] = true;
-            }
-            if (own) HIPCHK(hipEventRecord(c->done[k], ks));
-            ++c->launches;
+        if (!any) {
+            if (nonempty < 0) nonempty = pass;
+            break;
         }
-        for (int k = 0; k < NQ - 1; ++k)
-            if (n[k]) HIPCHK(hipStreamWaitEvent(s, c->done[k], 0));
+        use(cur);
+        unsigned blocks[NQ];
+        for (int k = 0; k < NQ; ++k) {
+            const uint64_t per_block = (uint64_t)WG * c->ipl;
+            const uint64_t want = (n[k] + per_block - 1) / per_block;
+            blocks[k] = n[k] ? (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)c->n_cu * c->occ[k])) : 0u;
+            if (blocks[k]) {
+                ++c->launches;
+                timed[k] = prof;
+            }
+        }
+        const epidmc_status st = launch_pass(c, P, blocks, prof ? c->ev : nullptr, s);
+        if (st != EPIDMC_OK) return st;
         cur = 1 - cur;
     }
+    c->last_passes = nonempty;
+    std::memcpy(c->prev_rows, rows, sizeof rows);
+    c->have_rows = true;
     if (c->tally_mode == 2) {
         HIPCHK(hipMemcpyAsync(c->host, cnt + 3 * NQ, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -916,6 +1066,101 @@ static epidmc_status run_chunk(epidmc_ctx *c, uint64_t h0, uint64_t h1, hipStrea
     return EPIDMC_OK;
 }
 
+// The chunks of a run [first, first + n) and the folds of its completed batches, on stream s.
+// capture: for a graph (device-driven passes only; no host synchronisation).
+static epidmc_status run_range(epidmc_ctx *c, uint64_t first, uint64_t n, hipStream_t s, bool capture, int *nchunks)
+{
+    const int B = c->batches;
+    const int ring = c->lay.ring;
+    uint64_t h = first;
+    uint64_t next_fold = 0;   // first batch not yet folded
+    int chunk = 0;
+    while (h < first + n) {
+        // a chunk ends at the chunk cap, and never spans more than `ring` batches
+        uint64_t h1 = std::min(first + n, h + c->lay.chunk);
+        if ((h >> 32) < 0xffffffffull) h1 = std::min(h1, ((h >> 32) + 1) << 32);   // one key per chunk
+        const uint64_t b_first = (h - first) * (uint64_t)B / n;
+        const uint64_t b_lim = b_first + (uint64_t)ring;   // batches [b_first, b_lim) may be in flight
+        if (b_lim < (uint64_t)B) h1 = std::min(h1, batch_start(first, n, B, b_lim));
+        REQUIRE(!capture || chunk < MAX_GRAPH_CHUNKS, EPIDMC_E_RANGE, "a captured run holds at most 32 chunks");
+        epidmc_status st = run_chunk(c, h, h1, s, capture, chunk);
+        if (st != EPIDMC_OK) return st;
+        ++chunk;
+        // fold the batches that are complete, in batch order (an incomplete batch keeps its slot)
+        const uint64_t b_done = (h1 >= first + n) ? (uint64_t)B : (h1 - first) * (uint64_t)B / n;
+        while (next_fold < b_done) {
+            int slots[MAX_SLOTS];
+            double nbs[MAX_SLOTS];
+            int k = 0;
+            for (; k < MAX_SLOTS && next_fold < b_done; ++k, ++next_fold) {
+                slots[k] = (int)(next_fold % (uint64_t)ring);
+                nbs[k] = (double)(batch_start(first, n, B, next_fold + 1) - batch_start(first, n, B, next_fold));
+            }
+            HIPCHK(launch_fold(c->P, slots, nbs, k, s));
+        }
+        h = h1;
+    }
+    if (nchunks) *nchunks = chunk;
+    return EPIDMC_OK;
+}
+
+static void drop_graph(epidmc_ctx *c)
+{
+    if (c->gx) (void)hipGraphExecDestroy(c->gx);
+    if (c->g) (void)hipGraphDestroy(c->g);
+    c->gx = nullptr;
+    c->g = nullptr;
+}
+
+// A run as one graph: captured on the first call for a history range, replayed on later
+// calls for the same range (the same histories again), then checked once on the host.
+static epidmc_status run_graph(epidmc_ctx *c, uint64_t first, uint64_t n, hipStream_t s)
+{
+    REQUIRE(c->tally_mode != 2 && !c->diag, EPIDMC_E_ARG, "graph runs need the FP64 or fixed-point tally and diagnostics off");
+    if (!c->gx || c->g_first != first || c->g_n != n) {
+        drop_graph(c);
+        {
+            const epidmc_status st = kind_streams(c);
+            if (st != EPIDMC_OK) return st;
+        }
+        if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));   // default priority
+        const int passes = c->graph_passes > 0 ? c->graph_passes : (c->last_passes > 0 ? c->last_passes + 2 : 12);
+        const int keep = c->graph_passes;
+        c->graph_passes = std::min(passes, MAX_DEV_PASSES);
+        HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        int nch = 0;
+        epidmc_status st = run_range(c, first, n, c->cap, true, &nch);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(c->cap, &g);
+        c->graph_passes = keep;
+        if (st != EPIDMC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        HIPCHK(ec);
+        c->g = g;
+        HIPCHK(hipGraphInstantiate(&c->gx, c->g, nullptr, nullptr, 0));
+        c->g_first = first;
+        c->g_n = n;
+        c->g_chunks = nch;
+        c->g_passes = passes;
+    }
+    HIPCHK(hipGraphLaunch(c->gx, s));
+    ++c->graph_launches;
+    HIPCHK(hipMemcpyAsync(c->host, c->ws + c->lay.ctl.off + CTL_LEFT, (size_t)c->g_chunks * (NQ + 1) * 4,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int ch = 0; ch < c->g_chunks; ++ch)
+        for (int k = 0; k < NQ; ++k)
+            if (c->host[ch * (NQ + 1) + k]) {
+                drop_graph(c);
+                return fail(c, EPIDMC_E_OVERFLOW, "a captured run needed more queue passes than the graph holds "
+                                                  "(the run's tally is incomplete: reset it, raise the graph's "
+                                                  "pass count and run again)");
+            }
+    return EPIDMC_OK;
+}
+
 extern "C" epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first, uint64_t n, void *stream)
 {
     if (!c) return EPIDMC_E_ARG;
@@ -929,44 +1174,18 @@ extern "C" epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first, uint64_t n, v
     }
     HIPCHK(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    const int B = c->batches;
-    const int ring = c->lay.ring;
     c->P.run_first = first;
     c->P.run_n = n;
-    c->P.run_batches = B;
-    c->P.ring = ring;
-    uint64_t h = first;
-    uint64_t next_fold = 0;   // first batch not yet folded
-    while (h < first + n) {
-        // a chunk ends at the chunk cap, and never spans more than `ring` batches
-        uint64_t h1 = std::min(first + n, h + c->lay.chunk);
-        if ((h >> 32) < 0xffffffffull) h1 = std::min(h1, ((h >> 32) + 1) << 32);   // one key per chunk
-        const uint64_t b_first = (h - first) * (uint64_t)B / n;
-        const uint64_t b_lim = b_first + (uint64_t)ring;   // batches [b_first, b_lim) may be in flight
-        if (b_lim < (uint64_t)B) h1 = std::min(h1, batch_start(first, n, B, b_lim));
-        epidmc_status st = run_chunk(c, h, h1, s);
-        if (st != EPIDMC_OK) return st;
-        // fold the batches that are complete
-        const uint64_t b_done = (h1 >= first + n) ? (uint64_t)B : (h1 - first) * (uint64_t)B / n;
-        // fold the complete batches, in batch order (an incomplete batch keeps its slot)
-        while (next_fold < b_done) {
-            int slots[MAX_SLOTS];
-            double nbs[MAX_SLOTS];
-            int k = 0;
-            for (; k < MAX_SLOTS && next_fold < b_done; ++k, ++next_fold) {
-                slots[k] = (int)(next_fold % (uint64_t)ring);
-                nbs[k] = (double)(batch_start(first, n, B, next_fold + 1) - batch_start(first, n, B, next_fold));
-            }
-            HIPCHK(launch_fold(c->P, slots, nbs, k, s));
-        }
-        h = h1;
-    }
+    c->P.run_batches = c->batches;
+    c->P.ring = c->lay.ring;
+    epidmc_status st = c->graph ? run_graph(c, first, n, s) : run_range(c, first, n, s, false, nullptr);
+    if (st != EPIDMC_OK) return st;
     HIPCHK(hipMemcpyAsync(c->host, c->P.err, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    epidmc_status st = check_error_word(c, c->host[0]);
+    st = check_error_word(c, c->host[0]);
     if (st != EPIDMC_OK) return st;
     c->n_total += (double)n;
-    c->b_total += (double)B;
+    c->b_total += (double)c->batches;
     return EPIDMC_OK;
 }
 

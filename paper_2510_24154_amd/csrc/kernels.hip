@@ -56,6 +56,18 @@ __device__ __forceinline__ void flush_stats(const Params &P, const Local &L, int
     }
 }
 
+// A pass launched without a host round trip starts every kind at its resident grid size;
+// the pass-start kernel has just written each queue's total, and the blocks beyond those the
+// total calls for (about P.ipl items per lane, as the host sizes grids) leave at once.  The
+// test is uniform over the block, before any barrier.
+__device__ __forceinline__ bool gated_off(const Params &P, int kind)
+{
+    if (!P.gated) return false;
+    const uint32_t n = __builtin_amdgcn_readfirstlane(P.cnt[kind]);
+    const uint32_t per = (uint32_t)WG * (uint32_t)P.ipl;
+    return blockIdx.x >= (n + per - 1) / per;
+}
+
 // ---------------------------------------------------------------------------------
 // placement of a particle given in the phantom frame (source particles, particles that
 // leave the phantom box): inside the box it stays; otherwise it flies on a straight line
@@ -472,6 +484,7 @@ __global__ __launch_bounds__(WG) void k_source(Params P)
 // extra wave hides latency.  It costs one spilled register.
 __global__ __launch_bounds__(WG, 6) void k_photon_phantom(Params P)
 {
+    if (gated_off(P, QGP)) return;
     // dynamic LDS: per wave two staging buffers (electrons for the phantom queue, photons
     // for the EPID queue).  The packed tables (16 KB of mu/rho, 32 KB of process fractions)
     // stay in global memory, where they live in L2.
@@ -620,6 +633,7 @@ __global__ __launch_bounds__(WG, 6) void k_photon_phantom(Params P)
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
 {
+    if (gated_off(P, QGE)) return;
     // dynamic LDS: per wave one staging buffer for the electrons set in motion in the EPID.
     // The layer tables (48 KB for four layers) are read from global memory, where they stay
     // in the caches: in LDS they made a workgroup too large to fit beside the phantom
@@ -764,6 +778,7 @@ __global__ __launch_bounds__(WG) void k_photon_epid(Params P)
 template <bool EPID>
 __global__ __launch_bounds__(WG) void k_electron(Params P)
 {
+    if (gated_off(P, EPID ? QEE : QEP)) return;
     extern __shared__ __align__(16) float lds[];
     __shared__ float s_zl[MAX_LAYERS + 1], s_rho[MAX_LAYERS], s_x0[MAX_PMAT + MAX_LAYERS];
     const int nm = EPID ? P.nl : P.nmat_ph;
@@ -1253,15 +1268,22 @@ __global__ void k_diag_check(Params P, uint32_t nh, unsigned long long *maxbits,
 // once; every workgroup also clears its share of the other set's fill counters and of the
 // consume heads (n16 16-byte words each), which the pass's appends and claims start from.
 static_assert(NSEG == 64 && WG == 64 * NQ, "one lane per segment, one wave per queue");
-__global__ void k_pass_start(Params P, const uint32_t *cnt, uint32_t *tot, uint4 *fills, uint4 *heads, uint32_t n16)
+__global__ void k_pass_start(Params P, const uint32_t *cnt, uint32_t *tot, uint4 *fills, uint4 *heads, uint32_t n16,
+                             uint32_t *hist)
 {
     if (blockIdx.x == 0) {
         const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
         uint32_t v = min(cnt[((uint32_t)k * NSEG + lane) * CSTRIDE], P.segcap[k]);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) tot[k] = v;
-        if (threadIdx.x == 0) tot[NQ] = *P.err;
+        if (lane == 0) {
+            tot[k] = v;
+            if (hist) hist[k] = v;   // kept per pass, for the host to read after device-driven passes
+        }
+        if (threadIdx.x == 0) {
+            tot[NQ] = *P.err;
+            if (hist) hist[NQ] = tot[NQ];
+        }
     }
     const uint4 z = make_uint4(0u, 0u, 0u, 0u);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += gridDim.x * blockDim.x) {
@@ -1561,11 +1583,11 @@ hipError_t launch_response(const RespArgs &A, hipStream_t s)
 }
 
 hipError_t launch_pass_start(const Params &P, const uint32_t *cnt, uint32_t *tot, uint32_t *fills, uint32_t *heads,
-                             size_t words, hipStream_t s)
+                             size_t words, hipStream_t s, uint32_t *hist)
 {
     if (words % 4 != 0 || cnt == nullptr || tot == nullptr || fills == nullptr || heads == nullptr) return hipErrorInvalidValue;
     const uint32_t n16 = (uint32_t)(words / 4);
-    hipLaunchKernelGGL(k_pass_start, dim3(8), dim3(WG), 0, s, P, cnt, tot, (uint4 *)fills, (uint4 *)heads, n16);
+    hipLaunchKernelGGL(k_pass_start, dim3(8), dim3(WG), 0, s, P, cnt, tot, (uint4 *)fills, (uint4 *)heads, n16, hist);
     return hipGetLastError();
 }
 

@@ -42,8 +42,8 @@ def z_gate(d1, v1, d2, v2, thr=0.10, k=1):
     return res
 
 
-def gamma_pass(ref, evl, pitch, dd=0.02, dta=0.2, thr=0.10, pitch_v=None):
-    """Fraction of reference pixels (D >= thr * max) with gamma <= 1.
+def gamma_map(ref, evl, pitch, dd=0.02, dta=0.2, pitch_v=None):
+    """Per-pixel global gamma of the evaluated image against the reference.
 
     ref, evl: 2D images on the same grid; pitch in cm (u = fast axis), dta in cm,
     dd as a fraction of max(ref).  The evaluated image is searched within a radius
@@ -52,7 +52,6 @@ def gamma_pass(ref, evl, pitch, dd=0.02, dta=0.2, thr=0.10, pitch_v=None):
     evl = np.asarray(evl, dtype=np.float64)
     pu, pv = pitch, (pitch if pitch_v is None else pitch_v)
     dcrit = dd * ref.max()
-    sel = ref >= thr * ref.max()
     ku = max(1, math.ceil(pu / (dta / 3.0)))
     kv = max(1, math.ceil(pv / (dta / 3.0)))
     best = np.full(ref.shape, np.inf)
@@ -66,7 +65,15 @@ def gamma_pass(ref, evl, pitch, dd=0.02, dta=0.2, thr=0.10, pitch_v=None):
             sh = ndimage.shift(evl, (-iv / kv, -iu / ku), order=1, mode="nearest")
             g2 = r2 + ((sh - ref) / dcrit) ** 2
             np.minimum(best, g2, out=best)
-    return float(np.mean(best[sel] <= 1.0))
+    return np.sqrt(best)
+
+
+def gamma_pass(ref, evl, pitch, dd=0.02, dta=0.2, thr=0.10, pitch_v=None):
+    """Fraction of reference pixels (D >= thr * max) with gamma <= 1 (see gamma_map)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    sel = ref >= thr * ref.max()
+    g = gamma_map(ref, evl, pitch, dd=dd, dta=dta, pitch_v=pitch_v)
+    return float(np.mean(g[sel] <= 1.0))
 
 
 def sigma_bar(mean, var, thr=0.5):
