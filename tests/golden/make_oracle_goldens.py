@@ -2,8 +2,12 @@
 compare with: the coupled workload's 256 x 256 x 128 phantom of 2 mm voxels, its spectrum and
 4-layer EPID at the native 0.39 mm pixel pitch, under narrow open fields.
 
-    python tests/golden/make_oracle_goldens.py [--threads N] [--only NAME]
+    python tests/golden/make_oracle_goldens.py [--threads N] [--only NAME] [--extend]
 
+--extend keeps an existing file made by the same oracle source with the same seed and runs only
+the history ids it lacks, [stored count, target count), adding their sums to the stored ones
+(the oracle's result for a history depends only on its id, so this equals one run over all ids
+up to the order of the sums).
 Calls only the CPU oracle (oracle/) and the seeded input generators (synth); each file holds
 the mean image (MeV per history per pixel), the variance of that mean, the history count, the
 oracle seed and the SHA-256 of the oracle source it came from, which a CPU test checks
@@ -30,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 GOLDENS = {
     "oracle_narrow_field_native": {"field": 1.0, "npx": 64, "histories": 16_000_000, "seed": 1001},
-    "oracle_narrow_field_g3": {"field": 1.5, "npx": 96, "histories": 120_000_000, "seed": 1002},
+    "oracle_narrow_field_g3": {"field": 1.5, "npx": 96, "histories": 160_000_000, "seed": 1002},
 }
 
 
@@ -38,28 +42,52 @@ def oracle_source_sha() -> str:
     return hashlib.sha256(open(os.path.join(ROOT, "oracle", "epid_oracle.c"), "rb").read()).hexdigest()
 
 
-def make(name: str, threads: int, parts: int = 40) -> str:
+def stored_sums(path, seed):
+    """(histories, sum, sum of squares) of an existing file made by the current oracle source
+    with this seed, or None.  Files without stored sums get them back from the mean and the
+    variance of the mean: s = n m, s2 = n (var (n - 1) + m^2)."""
+    if not os.path.exists(path):
+        return None
+    d = np.load(path)
+    if str(d["oracle_sha"]) != oracle_source_sha() or int(d["seed"]) != seed:
+        return None
+    n = int(d["histories"])
+    if "sum" in d.files:
+        return n, d["sum"].ravel(), d["sum2"].ravel()
+    m, v = d["mean"].ravel(), d["var"].ravel()
+    return n, n * m, n * (v * (n - 1) + m * m)
+
+
+def make(name: str, threads: int, parts: int = 40, extend: bool = False) -> str:
     import oracle
     from paper_2510_24154_amd import synth
     g = GOLDENS[name]
     cfg = synth.narrow_field(field=g["field"], npx=g["npx"])
     P = oracle.Prepared(cfg, g["seed"])
-    n, m = g["histories"], g["histories"] // parts
-    s = np.zeros(P.npix)
-    s2 = np.zeros(P.npix)
+    out = os.path.join(HERE, name + ".npz")
+    n = g["histories"]
+    start, s, s2 = 0, np.zeros(P.npix), np.zeros(P.npix)
+    if extend:
+        old = stored_sums(out, g["seed"])
+        if old is not None and old[0] <= n:
+            start, s, s2 = old
+            s, s2 = s.copy(), s2.copy()
+            print(f"[{name}] extending {start} stored histories to {n}", flush=True)
+    m = max(1, (n - start) // parts)
     t0 = time.time()
-    for i in range(parts):   # in parts, to report progress; the sums are the same
-        first = i * m
-        cnt = m if i < parts - 1 else n - first
+    first = start
+    while first < n:   # in parts, to report progress; the sums are the same
+        cnt = min(m, n - first)
         _, _, si, s2i, _ = oracle.run(cfg, cnt, seed=g["seed"], first=first, threads=threads, prepared=P)
         s += si
         s2 += s2i
-        print(f"[{name}] {first + cnt}/{n} histories, {time.time() - t0:.0f} s", flush=True)
+        first += cnt
+        print(f"[{name}] {first}/{n} histories, {time.time() - t0:.0f} s", flush=True)
     mean = s / n
     var = np.maximum((s2 / n - mean * mean) / (n - 1), 0.0)
-    out = os.path.join(HERE, name + ".npz")
-    np.savez_compressed(out, mean=mean.reshape(P.shape), var=var.reshape(P.shape), histories=n, seed=g["seed"],
-                        field_cm=g["field"], npx=g["npx"], pitch_cm=0.039, oracle_sha=oracle_source_sha())
+    np.savez_compressed(out, mean=mean.reshape(P.shape), var=var.reshape(P.shape), sum=s.reshape(P.shape),
+                        sum2=s2.reshape(P.shape), histories=n, seed=g["seed"], field_cm=g["field"], npx=g["npx"],
+                        pitch_cm=0.039, oracle_sha=oracle_source_sha())
     return out
 
 
@@ -67,6 +95,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--only", choices=list(GOLDENS), default=None)
+    ap.add_argument("--extend", action="store_true")
     a = ap.parse_args()
     for name in ([a.only] if a.only else list(GOLDENS)):
-        print(make(name, a.threads), flush=True)
+        print(make(name, a.threads, extend=a.extend), flush=True)
