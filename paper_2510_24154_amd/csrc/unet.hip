@@ -66,21 +66,22 @@ struct ConvArgs {
     int cg_shift, kg_total;  // log2(c_in / 8), k * k * c_in / 8
 };
 
-// A wave computes 64 pixels (4 row tiles) x NT*16 output channels; the 4 waves of a block
-// take consecutive pixel tiles and share the weight columns.
-template <int KS, int NT>
+// A wave computes MT*16 pixels (MT row tiles) x NT*16 output channels; the 4 waves of a block
+// take consecutive pixel tiles and share the weight columns.  MT = 1 gives four times the
+// blocks of MT = 4, for layers whose pixel count would otherwise leave CUs idle.
+template <int KS, int NT, int MT>
 __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, grp = lane >> 4;
-    const long long p0 = ((long long)blockIdx.x * 4 + wave) * 64;
+    const long long p0 = ((long long)blockIdx.x * 4 + wave) * (16 * MT);
     const int co0 = blockIdx.y * NT * 16;
     const int hw = a.h * a.wd;
-    int py[4], px[4];
-    long long pbase[4];
-    bool pv[4];
+    int py[MT], px[MT];
+    long long pbase[MT];
+    bool pv[MT];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < MT; ++m) {
         const long long p = p0 + m * 16 + row;
         pv[m] = p < a.P;
         const long long pc = pv[m] ? p : 0;
@@ -89,9 +90,9 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
         px[m] = r - py[m] * a.wd;
         pbase[m] = (long long)n * hw;
     }
-    f32x4 acc[4][NT];
+    f32x4 acc[MT][NT];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int kstride = a.kg_total * 8;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
         const int dy = KS == 3 ? tap / 3 - 1 : 0;
         const int dx = KS == 3 ? tap - (tap / 3) * 3 - 1 : 0;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < MT; ++m) {
             const int yy = py[m] + dy, xx = px[m] + dx;
             const bool ok = kv && pv[m] && yy >= 0 && yy < a.h && xx >= 0 && xx < a.wd;
             const long long off = ok ? ((pbase[m] + (long long)yy * a.wd + xx) * a.ldx + cg * 8) : 0;
@@ -125,17 +126,17 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
     // two register stages: the loads of step s+1 are in flight during step s's MFMAs.  The
     // step count is rounded up to even; a step past the end loads zeros.
     const int steps2 = (steps + 1) & ~1;
-    u32x4 A0[4], B0[NT], A1[4], B1[NT];
+    u32x4 A0[MT], B0[NT], A1[MT], B1[NT];
     load(0, A0, B0);
     for (int s = 0; s < steps2; s += 2) {
         load(s + 1, A1, B1);
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A0[m], B0[t], acc[m][t]);
         load(s + 2 < steps2 ? s + 2 : s + 1, A0, B0);
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A1[m], B1[t], acc[m][t]);
     }
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
         const int co = co0 + t * 16 + row;
         const float b = a.bias ? a.bias[co] : 0.0f;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const long long p = p0 + m * 16 + grp * 4 + r;
@@ -693,6 +694,20 @@ static inline unsigned nblocks(long long n, int per = WG) { return (unsigned)((n
 static int ilog2(int v) { int s = 0; while ((1 << s) < v) ++s; return s; }
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// compute units of the current device (cached per device)
+static int n_cu()
+{
+    static int cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
 static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_t *w, const float *bias, uint16_t *y,
                               int ldy, int cout, const uint16_t *gate, int ldg, int n, int h, int wd, int k, int relu,
                               hipStream_t s)
@@ -704,21 +719,35 @@ static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_
     a.cg_shift = ilog2(cin / 8);
     a.kg_total = k * k * cin / 8;
     if (a.P == 0) return hipSuccess;
-    const bool wide = cout % 64 == 0;
+    bool wide = cout % 64 == 0;
     if (k == 3 && cin % 32 == 0) {
         const int tx = (wd + TLW - 1) / TLW, ty = (h + TLH - 1) / TLH;
+        // 64 output channels per block unless that leaves fewer than two blocks per CU
+        if (wide && (long long)tx * ty * n * (cout / 64) < 2LL * n_cu()) wide = false;
         dim3 grid(tx * ty, n, cout / (wide ? 64 : 32));
         if (wide) hipLaunchKernelGGL((k_conv3_lds<4>), grid, dim3(WG), 0, s, a, tx);
         else hipLaunchKernelGGL((k_conv3_lds<2>), grid, dim3(WG), 0, s, a, tx);
         return hipGetLastError();
     }
-    dim3 grid(nblocks(a.P, 256), cout / (wide ? 64 : 32));
+    // four row tiles per wave unless that leaves fewer than two blocks per CU
+    const bool thin = (long long)nblocks(a.P, 256) * (cout / (wide ? 64 : 32)) < 2LL * n_cu();
+    dim3 grid(nblocks(a.P, thin ? 64 : 256), cout / (wide ? 64 : 32));
     if (k == 3) {
-        if (wide) hipLaunchKernelGGL((k_conv<3, 4>), grid, dim3(WG), 0, s, a);
-        else hipLaunchKernelGGL((k_conv<3, 2>), grid, dim3(WG), 0, s, a);
+        if (wide) {
+            if (thin) hipLaunchKernelGGL((k_conv<3, 4, 1>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_conv<3, 4, 4>), grid, dim3(WG), 0, s, a);
+        } else {
+            if (thin) hipLaunchKernelGGL((k_conv<3, 2, 1>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_conv<3, 2, 4>), grid, dim3(WG), 0, s, a);
+        }
     } else {
-        if (wide) hipLaunchKernelGGL((k_conv<1, 4>), grid, dim3(WG), 0, s, a);
-        else hipLaunchKernelGGL((k_conv<1, 2>), grid, dim3(WG), 0, s, a);
+        if (wide) {
+            if (thin) hipLaunchKernelGGL((k_conv<1, 4, 1>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_conv<1, 4, 4>), grid, dim3(WG), 0, s, a);
+        } else {
+            if (thin) hipLaunchKernelGGL((k_conv<1, 2, 1>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_conv<1, 2, 4>), grid, dim3(WG), 0, s, a);
+        }
     }
     return hipGetLastError();
 }
