@@ -297,6 +297,13 @@ __device__ __forceinline__ void transpose8(const u32x4 in[8], u32x4 out[8])
     }
 }
 
+// LDS position of 16-byte chunk `chunk` (8 pixels) of staged row `row`: the chunk index is
+// XOR-ed with bits 1-2 of row / 8.  A staging write stores one chunk of 16 rows that are 8
+// apart (two pixel groups x eight channel groups), which without the swizzle fall on four bank
+// groups of the 272-byte rows; with it, on sixteen.  A read takes one chunk of 16 consecutive
+// rows, which share the swizzle and stay on distinct banks.
+__device__ __forceinline__ int swz(int chunk, int row) { return chunk ^ ((row >> 3) & 6); }
+
 template <int KS, int WM>
 __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
 {
@@ -337,7 +344,7 @@ __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
             }
             transpose8(in, out);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) *(u32x4 *)(Gt + (c8 * 8 + c) * KPP + pg * 8) = out[c];
+            for (int c = 0; c < 8; ++c) *(u32x4 *)(Gt + (c8 * 8 + c) * KPP + swz(pg, c8 * 8 + c) * 8) = out[c];
         }
         for (int it = tid; it < XI; it += WG) {
             const int pg = it / (TN / 8), kl = it % (TN / 8);
@@ -362,18 +369,22 @@ __global__ __launch_bounds__(WG) void k_wgrad(WgArgs a)
             }
             transpose8(in, out);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) *(u32x4 *)(Xt + (kl * 8 + c) * KPP + pg * 8) = out[c];
+            for (int c = 0; c < 8; ++c) *(u32x4 *)(Xt + (kl * 8 + c) * KPP + swz(pg, kl * 8 + c) * 8) = out[c];
         }
         __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < KP / 32; ++ks) {
             u32x4 A[2], B[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                A[i] = *(const u32x4 *)(Gt + (wm * 32 + i * 16 + (lane & 15)) * KPP + ks * 32 + 8 * (lane >> 4));
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm * 32 + i * 16 + (lane & 15);
+                A[i] = *(const u32x4 *)(Gt + r * KPP + swz(ks * 4 + (lane >> 4), r) * 8);
+            }
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                B[j] = *(const u32x4 *)(Xt + (wn * 32 + j * 16 + (lane & 15)) * KPP + ks * 32 + 8 * (lane >> 4));
+            for (int j = 0; j < 2; ++j) {
+                const int r = wn * 32 + j * 16 + (lane & 15);
+                B[j] = *(const u32x4 *)(Xt + r * KPP + swz(ks * 4 + (lane >> 4), r) * 8);
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
