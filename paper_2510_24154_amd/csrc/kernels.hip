@@ -1088,9 +1088,8 @@ __global__ void k_fold(Params P, FoldArgs A)
 // an order that does not depend on scheduling, so that the image is the same on every run.
 // Records are binned by image element with a counting sort (arbitrary order within an
 // element), each element's records are then put in ascending order (a canonical order of the
-// same multiset of values), and one workgroup per tile of KT consecutive elements streams the
-// tile's records through LDS while each thread adds its element's records in that order in
-// FP32 with Kahan compensation.
+// same multiset of values), and one workgroup per tile of KT consecutive elements reduces the
+// tile's records in LDS to Kahan-compensated FP32 partials and the partials to the image.
 __global__ void k_rec_count(const uint32_t *pix, uint32_t n, uint32_t *count)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -1167,34 +1166,78 @@ __global__ void k_rec_order(const uint32_t *start, const uint32_t *end, float *s
     }
 }
 
-constexpr int KT = 256;       // image elements per tile (one per thread)
-constexpr int KCHUNK = 2048;  // records staged in LDS per round
+constexpr int KT = 256;                   // image elements per tile (one workgroup)
+constexpr int KSL = 8;                    // records per thread slice
+constexpr int KCHUNK = KT * KSL;          // records staged in LDS per round
 
-// one workgroup per tile: the tile's records are contiguous, [start[t0], end[t0 + KT - 1]);
-// they pass through LDS in coalesced chunks and thread j adds those of element t0 + j
+__device__ __forceinline__ void kahan_add(float &s, float &c, float v)
+{
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// One workgroup per tile of KT consecutive image elements, whose records are contiguous,
+// [start[t0], end[t0 + KT - 1]).  The records pass through LDS in chunks of KCHUNK; in each
+// chunk thread j owns the fixed slice of records [j * KSL, (j + 1) * KSL) and forms a
+// Kahan-compensated FP32 partial for every run of one element's records inside its slice
+// (kept in LDS at the position of the run's last record); then the thread of each element
+// adds its element's partials in slice order into its own compensated sum.  An element with
+// many records is thus summed by many threads at once, and every step has a fixed order, so
+// the tile's partials reduce to the same image on every run.
 __global__ __launch_bounds__(KT) void k_rec_kahan(const uint32_t *start, const uint32_t *end, const float *sorted,
                                                   uint32_t nimg, double *img)
 {
     __shared__ float chunk[KCHUNK];
+    __shared__ float2 part[KCHUNK];
+    __shared__ uint32_t st[KT + 1];      // record offsets of the tile's elements, st[KT] = tile end
     const uint32_t t0 = blockIdx.x * KT, i = t0 + threadIdx.x;
     const uint32_t last = min(t0 + KT, nimg) - 1;
     const uint32_t b0 = start[t0], b1 = end[last];
+    if (b1 == b0) return;   // uniform over the workgroup
+    st[threadIdx.x] = i < nimg ? start[i] : b1;
+    if (threadIdx.x == 0) st[KT] = b1;
     const uint32_t my0 = i < nimg ? start[i] : 0, my1 = i < nimg ? end[i] : 0;
-    float s = 0.0f, c = 0.0f;
+    float S = 0.0f, C = 0.0f;
     for (uint32_t base = b0; base < b1; base += KCHUNK) {
         const uint32_t lim = min(base + (uint32_t)KCHUNK, b1);
-        __syncthreads();
+        __syncthreads();   // st written; the previous chunk's partials consumed
         for (uint32_t k = base + threadIdx.x; k < lim; k += KT) chunk[k - base] = sorted[k];
         __syncthreads();
+        // slice partials
+        const uint32_t k0 = base + threadIdx.x * KSL, k1 = min(k0 + (uint32_t)KSL, lim);
+        if (k0 < k1) {
+            uint32_t lo = 0, hi = KT;   // the element of record k0: the last e with st[e] <= k0
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (st[mid] <= k0) lo = mid; else hi = mid;
+            }
+            uint32_t e = lo;
+            float s = 0.0f, c = 0.0f;
+            for (uint32_t k = k0; k < k1; ++k) {
+                if (k >= st[e + 1]) {
+                    part[k - 1 - base] = make_float2(s, c);
+                    s = 0.0f;
+                    c = 0.0f;
+                    while (k >= st[e + 1]) ++e;
+                }
+                kahan_add(s, c, chunk[k - base]);
+            }
+            part[k1 - 1 - base] = make_float2(s, c);
+        }
+        __syncthreads();
+        // the element's partials, slice by slice
         const uint32_t lo = max(my0, base), hi = min(my1, lim);
-        for (uint32_t k = lo; k < hi; ++k) {
-            const float y = chunk[k - base] - c;
-            const float t = s + y;
-            c = (t - s) - y;
-            s = t;
+        if (lo < hi) {
+            for (uint32_t q = (lo - base) / KSL; q <= (hi - 1 - base) / KSL; ++q) {
+                const uint32_t kl = min(hi, base + (q + 1) * (uint32_t)KSL) - 1;
+                const float2 p = part[kl - base];
+                kahan_add(S, C, p.x - p.y);
+            }
         }
     }
-    if (i < nimg && my1 > my0) img[i] += (double)s - (double)c;
+    if (i < nimg && my1 > my0) img[i] += (double)S - (double)C;
 }
 
 __global__ void k_image(Params P, double n, double nbatch, double *mean, double *var)
