@@ -205,6 +205,28 @@ def test_fixed_point_same_on_a_side_stream_with_profiling(E):
     assert all(ms > 0 for ms in c["kernel_ms"]), c["kernel_ms"]
 
 
+@pytest.mark.parametrize("n", [2, 3, 63, 65, 1025, 4097])
+def test_ragged_history_counts(E, n):
+    """Runs far below a wave or a chunk, and chunks with a one-history tail: the fixed-point
+    image with 1024-history chunks equals the one-chunk image bit for bit, every history
+    closes its energy ledger, and a run with fewer histories than variance batches (or none)
+    is refused."""
+    cfg = synth.coupled_hetero_small()
+    m0, v0, _ = gpu_image(E, cfg, n, seed=41, tally=1, batches=2, max_chunk=1024)
+    m1, v1, _ = gpu_image(E, cfg, n, seed=41, tally=1, batches=2, max_chunk=1 << 20)
+    assert np.array_equal(m0, m1) and np.array_equal(v0, v1)
+    assert np.isfinite(m0).all() and (m0 >= 0).all() and (v0 >= 0).all()
+    eng = E.Engine(0, seed=41).configure(cfg, tally=1, batches=2, max_chunk=1024, diag=True)
+    eng.bind()
+    eng.run(n, first=7)
+    c = eng.counters()
+    assert c["error_word"] == 0 and c["max_ledger_resid"] < 1e-9
+    assert c["e_in"] > 0 and c["e_deposited"] == pytest.approx(c["e_in"], rel=1e-12)
+    for bad in (0, 1):
+        with pytest.raises(E.EpidmcError):
+            eng.run(bad)
+
+
 def test_tally_modes_agree(E):
     """Same seed, same trajectories: FP64 atomics, int64 fixed point and FP32 Kahan records
     give the same image up to their rounding (fixed point 2^-32 MeV per deposit, FP32)."""
