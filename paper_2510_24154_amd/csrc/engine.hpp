@@ -94,7 +94,8 @@ struct Params {
     float pitch_u, pitch_v, ipu, ipv, s_pix;
     float ph_to_epid_z;         // front_z - oz: the EPID plane in phantom-local z
 
-    // tables (global memory copies, staged to LDS by the kernels)
+    // tables in global memory (the electron kernels copy theirs to LDS; the photon kernels
+    // read them through the caches)
     const float *ph_tab;        // [MAX_PMAT + MAX_LAYERS][3][NB_PH]: mu/rho, f_compton, f_compton+photo
     const float *ph_maj;        // [NB_PH] phantom majorant, 1/cm
     const float4 *ph_mu4;       // [NB_PH] mu/rho of the four phantom material slots (0 when unused)

@@ -4,7 +4,9 @@
 // per non-empty queue (photons / electrons x phantom / EPID); a wave keeps its 64 lanes
 // busy by refilling idle lanes from its queue, advances every lane by one step per loop
 // iteration, and appends secondaries and region changes to next-pass queues with one
-// atomic per wave.  Cross-section tables are staged in LDS once per workgroup.
+// atomic per wave.  The electron kernels stage their cross-section tables in LDS once per
+// workgroup; the photon kernels read theirs through the caches, where they stay resident
+// (in LDS they cost the Woodcock kernel resident waves and made it slower).
 //
 // Physics per step (the paper's physics class, Sec. 2.1.2; where the paper leaves a model
 // open, the engine and the CPU oracle implement the same explicit reading):
