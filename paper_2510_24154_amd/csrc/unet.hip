@@ -61,15 +61,17 @@ struct ConvArgs {
     const uint16_t *x, *w, *gate;
     const float *bias;
     uint16_t *y;
+    uint16_t *pool;          // k_conv3_lds only: also the 2 x 2 average of y (h, w even), or null
     long long P;             // pixels n * h * w
-    int ldx, ldy, ldg, cin, cout, h, wd, relu;
+    int ldx, ldy, ldg, cin, cout, h, wd, relu, ldp;
+    int up;                  // k_conv only: y is the 2x nearest-neighbour upsampling (2h x 2w) of the output
     int cg_shift, kg_total;  // log2(c_in / 8), k * k * c_in / 8
 };
 
 // A wave computes MT*16 pixels (MT row tiles) x NT*16 output channels; the 4 waves of a block
 // take consecutive pixel tiles and share the weight columns.  MT = 1 gives four times the
 // blocks of MT = 4, for layers whose pixel count would otherwise leave CUs idle.
-template <int KS, int NT, int MT>
+template <int KS, int NT, int MT, bool UP = false>
 __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -141,6 +143,32 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
             for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A1[m], B1[t], acc[m][t]);
     }
     // lane holds rows 4*grp + r of each 16-pixel tile, column `row` of each channel tile
+    if (UP) {
+        // each output value goes to its 2 x 2 block of the upsampled image (no gate)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long p = p0 + m * 16 + grp * 4 + r;
+                if (p >= a.P) continue;
+                const int n = (int)(p / hw), rr = (int)(p - (long long)n * hw);
+                const int yi = rr / a.wd, xi = rr - yi * a.wd;
+                const long long q = ((long long)n * 2 * a.h + 2 * yi) * (2 * a.wd) + 2 * xi;
+                const long long q2 = q + 2 * a.wd;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int co = co0 + t * 16 + row;
+                    float v = acc[m][t][r] + (a.bias ? a.bias[co] : 0.0f);
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    const uint16_t o = f2bf(v);
+                    a.y[q * a.ldy + co] = o;
+                    a.y[(q + 1) * a.ldy + co] = o;
+                    a.y[q2 * a.ldy + co] = o;
+                    a.y[(q2 + 1) * a.ldy + co] = o;
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int co = co0 + t * 16 + row;
@@ -263,6 +291,31 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
                 if (a.gate && !(bf2f(a.gate[p * a.ldg + co]) > 0.0f)) v = 0.0f;
                 a.y[p * a.ldy + co] = f2bf(v);
             }
+        if (a.pool) {
+            // the 2 x 2 average of the stored (BF16) outputs, added in the order of a separate
+            // pooling pass: a wave's two rows are one pooled row, and a lane holds both
+            // columns of each pair (r = 0, 1 and 2, 3) in both rows (m and m + 2)
+            const int y = ty0 + 2 * wave;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+                for (int rp = 0; rp < 2; ++rp) {
+                    const int x = tx0 + hh * 16 + grp * 4 + 2 * rp;
+                    if (y >= a.h || x >= a.wd) continue;
+                    float s = 0.0f;
+                    const int ms[2] = {hh, hh + 2};
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            float v = acc[ms[i]][t][2 * rp + j] + b;
+                            if (a.relu) v = fmaxf(v, 0.0f);
+                            s += bf2f(f2bf(v));
+                        }
+                    const long long q = ((long long)img * (a.h / 2) + y / 2) * (a.wd / 2) + x / 2;
+                    a.pool[q * a.ldp + co] = f2bf(0.25f * s);
+                }
+        }
     }
 }
 
@@ -719,19 +772,27 @@ static int n_cu()
     return cache[dev];
 }
 
+// y = act(conv(x)); with `pool`, also the 2 x 2 average pooling of y into pool (h and w
+// even, no gate), inside the convolution's epilogue where the LDS-tiled kernel runs, else by
+// a separate pass; with `up` (1 x 1 convolutions, no gate), y is the output upsampled 2x by
+// nearest neighbour, written by the epilogue
 static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_t *w, const float *bias, uint16_t *y,
                               int ldy, int cout, const uint16_t *gate, int ldg, int n, int h, int wd, int k, int relu,
-                              hipStream_t s)
+                              hipStream_t s, uint16_t *pool = nullptr, int ldp = 0, int up = 0)
 {
     ConvArgs a;
-    a.x = x; a.w = w; a.gate = gate; a.bias = bias; a.y = y;
+    a.x = x; a.w = w; a.gate = gate; a.bias = bias; a.y = y; a.pool = nullptr;
     a.P = (long long)n * h * wd;
-    a.ldx = ldx; a.ldy = ldy; a.ldg = ldg; a.cin = cin; a.cout = cout; a.h = h; a.wd = wd; a.relu = relu;
+    a.ldx = ldx; a.ldy = ldy; a.ldg = ldg; a.cin = cin; a.cout = cout; a.h = h; a.wd = wd; a.relu = relu; a.ldp = ldp;
+    a.up = up;
     a.cg_shift = ilog2(cin / 8);
     a.kg_total = k * k * cin / 8;
     if (a.P == 0) return hipSuccess;
+    if (pool && (h % 2 || wd % 2 || gate || cout % 8 || up)) return hipErrorInvalidValue;
+    if (up && (k != 1 || gate)) return hipErrorInvalidValue;
     bool wide = cout % 64 == 0;
     if (k == 3 && cin % 32 == 0) {
+        a.pool = pool;
         const int tx = (wd + TLW - 1) / TLW, ty = (h + TLH - 1) / TLH;
         // 64 output channels per block unless that leaves fewer than two blocks per CU
         if (wide && (long long)tx * ty * n * (cout / 64) < 2LL * n_cu()) wide = false;
@@ -751,6 +812,14 @@ static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_
             if (thin) hipLaunchKernelGGL((k_conv<3, 2, 1>), grid, dim3(WG), 0, s, a);
             else hipLaunchKernelGGL((k_conv<3, 2, 4>), grid, dim3(WG), 0, s, a);
         }
+    } else if (up) {
+        if (wide) {
+            if (thin) hipLaunchKernelGGL((k_conv<1, 4, 1, true>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_conv<1, 4, 4, true>), grid, dim3(WG), 0, s, a);
+        } else {
+            if (thin) hipLaunchKernelGGL((k_conv<1, 2, 1, true>), grid, dim3(WG), 0, s, a);
+            else hipLaunchKernelGGL((k_conv<1, 2, 4, true>), grid, dim3(WG), 0, s, a);
+        }
     } else {
         if (wide) {
             if (thin) hipLaunchKernelGGL((k_conv<1, 4, 1>), grid, dim3(WG), 0, s, a);
@@ -759,6 +828,11 @@ static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_
             if (thin) hipLaunchKernelGGL((k_conv<1, 2, 1>), grid, dim3(WG), 0, s, a);
             else hipLaunchKernelGGL((k_conv<1, 2, 4>), grid, dim3(WG), 0, s, a);
         }
+    }
+    if (pool) {
+        const long long items = (long long)n * (h / 2) * (wd / 2) * (cout / 8);
+        hipLaunchKernelGGL(k_pool, dim3(nblocks(items)), dim3(WG), 0, s, (const uint16_t *)y, ldy, pool, ldp, cout, n, h,
+                           wd);
     }
     return hipGetLastError();
 }
@@ -852,7 +926,7 @@ struct epidmc_unet {
     struct {
         Buf X, x0, tgt, scale, sumpart, headpart, wgs;
         Buf theta, m, v, grad, wf, wb, ema;
-        Buf ea[LEVELS], cat[LEVELS - 1], eb3, pl[LEVELS - 1], ul[LEVELS - 1], da[LEVELS - 1], db[LEVELS - 1];
+        Buf ea[LEVELS], cat[LEVELS - 1], eb3, pl[LEVELS - 1], da[LEVELS - 1], db[LEVELS - 1];
         Buf gdb[LEVELS - 1], gda[LEVELS - 1], gcat[LEVELS - 1], gul[LEVELS - 1], geb[LEVELS], gea[LEVELS],
             gp[LEVELS - 1];
         size_t total = 0;
@@ -955,7 +1029,6 @@ static size_t plan(epidmc_unet *u, int n, int h, int w)
         take(y.gcat[l], P(l) * 2 * chan(l) * 2);
         take(y.pl[l], P(l + 1) * chan(l) * 2);
         take(y.gp[l], P(l + 1) * chan(l) * 2);
-        take(y.ul[l], P(l + 1) * chan(l) * 2);
         take(y.gul[l], P(l + 1) * chan(l) * 2);
         take(y.da[l], P(l) * chan(l) * 2);
         take(y.gda[l], P(l) * chan(l) * 2);
@@ -1010,12 +1083,8 @@ static hipError_t forward(epidmc_unet *u, int n, hipStream_t s)
         uint16_t *out = l < LEVELS - 1 ? at<uint16_t>(u, y.cat[l]) : at<uint16_t>(u, y.eb3);
         const int ldo = l < LEVELS - 1 ? 2 * c : c;
         if ((e = launch_conv(at<uint16_t>(u, y.ea[l]), c, c, wf + B.ow, th + B.ob, out, ldo, c, nullptr, 0, n, hl, wl,
-                             3, 1, s)) != hipSuccess) return e;
-        if (l < LEVELS - 1) {
-            const long long items = (long long)n * (hl / 2) * (wl / 2) * (c / 8);
-            hipLaunchKernelGGL(k_pool, dim3(nblocks(items)), dim3(WG), 0, s, (const uint16_t *)out, ldo,
-                               at<uint16_t>(u, y.pl[l]), c, c, n, hl, wl);
-        }
+                             3, 1, s, l < LEVELS - 1 ? at<uint16_t>(u, y.pl[l]) : nullptr, c)) != hipSuccess)
+            return e;
     }
     for (int l = LEVELS - 2; l >= 0; --l) {
         const int c = chan(l), hl = u->h >> l, wl = u->w >> l;
@@ -1023,11 +1092,10 @@ static hipError_t forward(epidmc_unet *u, int n, hipStream_t s)
         const Layer &A = u->L[find(u, (std::string("d") + char('0' + l) + "a").c_str())];
         const Layer &B = u->L[find(u, (std::string("d") + char('0' + l) + "b").c_str())];
         const uint16_t *in = l == LEVELS - 2 ? at<uint16_t>(u, y.eb3) : at<uint16_t>(u, y.db[l + 1]);
-        if ((e = launch_conv(in, chan(l + 1), chan(l + 1), wf + U.ow, th + U.ob, at<uint16_t>(u, y.ul[l]), c, c,
-                             nullptr, 0, n, hl / 2, wl / 2, 1, 0, s)) != hipSuccess) return e;
-        const long long items = (long long)n * (hl / 2) * (wl / 2) * (c / 8);
-        hipLaunchKernelGGL(k_upsample, dim3(nblocks(items)), dim3(WG), 0, s, (const uint16_t *)at<uint16_t>(u, y.ul[l]),
-                           c, at<uint16_t>(u, y.cat[l]) + c, 2 * c, c, n, hl / 2, wl / 2);
+        // the 1 x 1 up-convolution writes its 2x upsampled output straight into the second half
+        // of the concatenation
+        if ((e = launch_conv(in, chan(l + 1), chan(l + 1), wf + U.ow, th + U.ob, at<uint16_t>(u, y.cat[l]) + c, 2 * c,
+                             c, nullptr, 0, n, hl / 2, wl / 2, 1, 0, s, nullptr, 0, 1)) != hipSuccess) return e;
         if ((e = launch_conv(at<uint16_t>(u, y.cat[l]), 2 * c, 2 * c, wf + A.ow, th + A.ob, at<uint16_t>(u, y.da[l]),
                              c, c, nullptr, 0, n, hl, wl, 3, 1, s)) != hipSuccess) return e;
         if ((e = launch_conv(at<uint16_t>(u, y.da[l]), c, c, wf + B.ow, th + B.ob, at<uint16_t>(u, y.db[l]), c, c,
