@@ -304,6 +304,14 @@ epidmc_status epidmc_debug_philox(epidmc_ctx *c, const uint32_t *dev_ctr, uint32
  * accompanies a kind-0 sample (uniform on (0, 1)).  n samples into dev_out. */
 epidmc_status epidmc_debug_sample(epidmc_ctx *c, int kind, double p0, double p1, double p2, float *dev_out,
                                   uint64_t n, void *stream);
+/* Test entry point for the queue-overflow path: the capacity of every segment of queue
+ * `kind` (1 electrons in the phantom, 2 photons in the EPID, 3 electrons in the EPID; the
+ * phantom photon queue, which the source fills by slot, cannot be changed) in particles, from
+ * the next epidmc_bind_workspace on (the call unbinds); 0 restores the capacity derived from
+ * max_chunk_histories, at most 2^24.  A pass whose appends exceed a segment stores nothing
+ * beyond it, drops the particles that do not fit and latches the overflow, which the run
+ * returns as EPIDMC_E_OVERFLOW; the image of such a run is incomplete until the next bind. */
+epidmc_status epidmc_debug_queue_capacity(epidmc_ctx *c, int kind, uint32_t per_segment);
 /* Deposit records of the last chunk transported in the Kahan tally mode, the tally's raw
  * input (a test entry point: re-binned on the host they must give the tally): up to cap
  * records copied on `stream` to dev_pix (image element = variance-batch slot * npx_u * npx_v

@@ -83,6 +83,7 @@ EXPORTS = [
     "epidmc_radiological_thickness", "epidmc_field_size", "epidmc_dose_response",
     "epidmc_resample_response_table",
     "epidmc_debug_philox", "epidmc_debug_sample", "epidmc_debug_table", "epidmc_debug_records",
+    "epidmc_debug_queue_capacity",
     "epidmc_microbench",
 ] + DN_EXPORTS
 
@@ -130,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         "epidmc_debug_sample": [vp, i32, f64, f64, f64, vp, u64, vp],
         "epidmc_debug_table": [vp, i32, i32, vp, vp, u64, vp],
         "epidmc_debug_records": [vp, vp, vp, u64, ct.POINTER(u64), vp],
+        "epidmc_debug_queue_capacity": [vp, i32, u32],
         "epidmc_microbench": [i32, vp, ct.c_size_t, i32, u32, u32, vp],
     }
     for name, args in sig.items():
@@ -366,6 +368,11 @@ class Engine:
         self._check(self.L.epidmc_debug_sample(self.h, int(kind), float(p0), float(p1), float(p2),
                                                ct.c_void_p(out.data_ptr()), int(n), self._stream()))
         return out.cpu().numpy().reshape(n, width) if width > 1 else out.cpu().numpy()
+
+    def debug_queue_capacity(self, kind, per_segment):
+        """Test hook: particles per segment of queue `kind` (1-3) from the next bind on (0: the
+        size derived from the chunk).  Unbinds."""
+        self._check(self.L.epidmc_debug_queue_capacity(self.h, int(kind), int(per_segment)))
 
     def debug_records(self, cap):
         """Kahan-mode deposit records of the last chunk: (image element, MeV) as numpy arrays

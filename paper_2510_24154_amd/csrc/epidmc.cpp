@@ -145,6 +145,7 @@ struct epidmc_ctx {
     // accumulated
     double n_total = 0, b_total = 0;
     uint64_t launches = 0, queue_peak = 0;
+    uint32_t q_override[NQ] = {0, 0, 0, 0};   // test hook: particles per segment (0: derived)
 };
 
 static epidmc_status fail(epidmc_ctx *c, epidmc_status s, const std::string &m)
@@ -552,6 +553,7 @@ static Layout make_layout(const epidmc_ctx *c)
     constexpr uint32_t MIN_SEGCAP = 16384;
     for (int k = 0; k < NQ; ++k) {
         L.segcap[k] = std::max<uint32_t>((L.cap[k] + NSEG - 1) / NSEG, MIN_SEGCAP);
+        if (c->q_override[k]) L.segcap[k] = c->q_override[k];
         L.cap[k] = L.segcap[k] * NSEG;
     }
     L.rec_cap = c->tally_mode == 2 ? (uint32_t)(8 * H + 4096) : 0;
@@ -1462,6 +1464,17 @@ extern "C" epidmc_status epidmc_debug_sample(epidmc_ctx *c, int kind, double p0,
         return EPIDMC_OK;
     }
     HIPCHK(launch_dbg_sample(P, kind, (float)p0, (float)p1, (float)p2, out, n, (hipStream_t)stream));
+    return EPIDMC_OK;
+}
+
+extern "C" epidmc_status epidmc_debug_queue_capacity(epidmc_ctx *c, int kind, uint32_t per_segment)
+{
+    if (!c) return EPIDMC_E_ARG;
+    // the source writes the phantom photon queue by slot, so only the other kinds can shrink
+    REQUIRE(kind >= 1 && kind < NQ, EPIDMC_E_ARG, "kind in [1, 3]");
+    REQUIRE(per_segment <= (1u << 24), EPIDMC_E_RANGE, "at most 2^24 particles per segment");
+    c->q_override[kind] = per_segment;
+    unbind(c);
     return EPIDMC_OK;
 }
 

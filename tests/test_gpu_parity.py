@@ -227,6 +227,32 @@ def test_ragged_history_counts(E, n):
             eng.run(bad)
 
 
+def test_queue_overflow_is_reported_and_contained(E):
+    """A phantom-electron queue shrunk to 8 particles per segment (the library's test hook)
+    cannot take a pass's appends: the run stores nothing past the segments, drops what does not
+    fit and returns EPIDMC_E_OVERFLOW (-7).  After a bind with the derived size the engine's
+    fixed-point image equals a fresh engine's bit for bit, and its largest pass stays far
+    below the derived capacity."""
+    cfg = synth.coupled_hetero_small()
+    n, chunk = 100_000, 1 << 16
+    eng = E.Engine(0, seed=51).configure(cfg, tally=1, batches=4, max_chunk=chunk)
+    eng.debug_queue_capacity(1, 8)
+    eng.bind()
+    with pytest.raises(E.EpidmcError) as ei:
+        eng.run(n)
+    assert ei.value.code == -7 and "queue overflow" in str(ei.value)
+    with pytest.raises(E.EpidmcError):
+        eng.debug_queue_capacity(0, 8)   # the source fills the phantom photon queue by slot
+    eng.debug_queue_capacity(1, 0)
+    eng.bind()
+    eng.run(n)
+    m1, v1 = (t.cpu().numpy() for t in eng.image())
+    assert eng.counters()["queue_peak"] < 2 * chunk
+    m0, v0, _ = gpu_image(E, cfg, n, seed=51, tally=1, batches=4, max_chunk=chunk)
+    assert m0.sum() > 0
+    assert np.array_equal(m1, m0) and np.array_equal(v1, v0)
+
+
 def test_tally_modes_agree(E):
     """Same seed, same trajectories: FP64 atomics, int64 fixed point and FP32 Kahan records
     give the same image up to their rounding (fixed point 2^-32 MeV per deposit, FP32)."""
