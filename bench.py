@@ -366,6 +366,19 @@ def equal_rmse(rmse, seconds, denoised_rmse, denoised_s):
     return n_eq, n_eq / rate / denoised_s, e_ref2
 
 
+def run_to_1pct(eng, torch, step):
+    """Run from history id 0 until sigma-bar (pixels >= 50% of max) <= 1%, one check per
+    `step` histories; the wall time, histories and sigma-bars (the 10% selection too)."""
+    torch.cuda.synchronize()
+    tm = time.perf_counter()
+    done, sb1 = eng.run_until(0.01, thr=0.5, first=0, step=step, max_hist=2000 * step)
+    torch.cuda.synchronize()
+    tmd = time.perf_counter() - tm
+    return {"s_to_1pct": round(tmd, 2), "histories": done, "sigma_bar": round(sb1, 5),
+            "sigma_bar_10pct": round(eng.sigma_bar(0.1), 5), "step_histories": step,
+            "histories_per_s": round(done / tmd, 1)}
+
+
 def host_cpu():
     """The host's CPU facts: nproc, the CPUs this process may run on, the cgroup CPU quota
     (if any) and the lscpu model name."""
@@ -487,7 +500,10 @@ def parse():
     ap.add_argument("--dn-mixed", type=int, default=1,
                     help="1: every other training field is a thorax-like phantom under a multi-segment field")
     ap.add_argument("--t1-measured", action="store_true",
-                    help="also run the coupled workload until sigma-bar <= 1% (about 80 s) and time it")
+                    help="also run the workload until sigma-bar <= 1% and time it (a segmented field is "
+                         "delivered again with new history ids until then; about 150 s for imrt40)")
+    ap.add_argument("--no-t1-paper", action="store_true",
+                    help="skip the measured time to 1% at the paper's pixel pitch (imrt40_2p5mm, about 35 s)")
     return ap.parse_args()
 
 
@@ -640,23 +656,28 @@ def main():
     roof["gathers_per_s"] = round(gathers_ps, 1) if gathers_ps else None
 
     measured = None
-    if a.t1_measured and segmented:
-        print("--t1-measured runs on the coupled workload only (a field's ids end at its total)", file=sys.stderr)
-    elif a.t1_measured:
-        # time to a 1% image measured directly: fresh tally, steps of 2e9 histories (ids
-        # continue past 2^32), sigma-bar checked after each step
+    if a.t1_measured:
+        # time to a 1% image measured directly: fresh tally, sigma-bar checked after each step
+        # (a segmented field: one whole delivery per step, history ids continuing past the
+        # field's total, i.e. new independent deliveries; otherwise steps of 2e9 histories)
         eng.set_profiling(False)
         eng.reset()
         torch.cuda.synchronize()
-        step = 2_000_000_000
-        tm = time.perf_counter()
-        done, sb1 = eng.run_until(0.01, thr=0.5, first=h, step=step, max_hist=1_000_000_000_000)
-        torch.cuda.synchronize()
-        tmd = time.perf_counter() - tm
-        measured = {"s_to_1pct": round(tmd, 2), "histories": done, "sigma_bar": round(sb1, 5),
-                    "sigma_bar_10pct": round(eng.sigma_bar(0.1), 5), "step_histories": step,
-                    "first_history": h}
+        measured = run_to_1pct(eng, torch, n_step if segmented else 2_000_000_000)
         print(json.dumps({"t1pct_measured": measured}), file=sys.stderr, flush=True)
+    del eng
+    torch.cuda.empty_cache()
+    paper_t1 = None
+    if a.workload == "imrt40" and not a.no_t1_paper:
+        cfg_p = synth.with_histories_scaled(synth.imrt_field(npx=(160, 160), pitch=0.25), 1_000_000_000)
+        eng_p = E.Engine(0, seed=2).configure(cfg_p, batches=BATCHES, max_chunk=CHUNK)
+        eng_p.bind()
+        eng_p.set_passes(dpasses, ipl)
+        paper_t1 = run_to_1pct(eng_p, torch, 1_000_000_000)
+        paper_t1["workload"] = WORKLOADS["imrt40_2p5mm"][0]
+        print(json.dumps({"t1pct_measured_at_paper_pitch": paper_t1}), file=sys.stderr, flush=True)
+        del eng_p
+        torch.cuda.empty_cache()
 
     dn = None
     if not a.no_denoiser:
@@ -705,6 +726,7 @@ def main():
         "cpu_baseline": cpu,
         "dose_response": response,
         "t1pct_measured": measured,
+        "t1pct_measured_at_paper_pitch": paper_t1,
         "denoiser": dn,
         "counters": {k: c[k] for k in ("woodcock_steps", "e_steps_phantom", "e_steps_epid", "epid_photon_steps",
                                        "tally_deposits", "launches", "kernel_ms", "kernel_launches",

@@ -190,7 +190,8 @@ epidmc_status epidmc_set_source_phsp(epidmc_ctx *c, const epidmc_particle *p, ui
 /* MLC apertures on the beam's aperture plane: leaf pair k of segment s spans y in
  * [y0 + k*w, y0 + (k+1)*w) and is open for x in [a[s*n_pairs+k], b[s*n_pairs+k]]
  * (the apertures of Sec. 2.1.1, taken from the plan).  Global history ids are assigned
- * to segments consecutively by n_hist[s]; with one segment n_hist is ignored. */
+ * to segments consecutively by n_hist[s] (ids past their total repeat the delivery, see
+ * epidmc_run); with one segment n_hist is ignored. */
 epidmc_status epidmc_set_segments(epidmc_ctx *c, int n_segments, int n_pairs, float leaf_width, float y0,
                                   const float *a, const float *b, const uint64_t *n_hist);
 /* Tally: mode, variance batches per run call (>= 2; 64 or more recommended), and the
@@ -235,7 +236,10 @@ epidmc_status epidmc_bind_workspace(epidmc_ctx *c, void *dev_ptr, size_t bytes, 
  * into the configured number of variance batches, and fold them into the tally.
  * Returns after the work has completed.  History ids are 64-bit: the random stream of
  * history h is keyed by the seed and h's high 32 bits, and counted by its low 32 bits, so
- * ids below 2^32 keep the plain seed key.  A segmented field's ids stay below its total.
+ * ids below 2^32 keep the plain seed key.  A segmented field of total T histories takes
+ * ids [0, T) as one delivery; an id h >= T belongs to delivery h / T and samples the
+ * segment of h mod T with its own random stream, so consecutive id ranges deliver the field
+ * again with independent histories.
  * Within a queue pass the four particle kinds run concurrently: three on streams the
  * context creates (default priority) and the last on `stream`, which waits for the
  * others before the next pass. */

@@ -1172,7 +1172,7 @@ extern "C" epidmc_status epidmc_run(epidmc_ctx *c, uint64_t first, uint64_t n, v
     if (c->n_seg > 1 && c->n_phsp == 0) {
         uint64_t tot = 0;
         for (uint64_t v : c->seg_hist) tot += v;
-        REQUIRE(first + n <= tot, EPIDMC_E_RANGE, "histories beyond the segments' total");
+        REQUIRE(tot > 0, EPIDMC_E_NOT_READY, "the segments hold no histories");
     }
     HIPCHK(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;

@@ -408,10 +408,14 @@ __device__ __forceinline__ void source_particle(const Params &P, unsigned long l
     p.E = fmaf(r.z, P.sp_hi[i] - P.sp_lo[i], P.sp_lo[i]);
     int s = 0;
     if (P.n_seg > 1) {
+        // ids past the field's total deliver it again: the segment of h mod total, with the
+        // history's own random stream
+        const unsigned long long tot = P.seg_end[P.n_seg - 1];
+        const unsigned long long hs = h < tot ? h : h % tot;
         int lo = 0, hi = P.n_seg - 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (h < P.seg_end[mid]) hi = mid; else lo = mid + 1;
+            if (hs < P.seg_end[mid]) hi = mid; else lo = mid + 1;
         }
         s = lo;
     }

@@ -405,6 +405,48 @@ def test_segmented_field_beyond_2_32_histories(E):
     np.testing.assert_array_equal(imgs[0], imgs[1])
 
 
+def test_ids_past_the_total_deliver_the_field_again(E):
+    """Ids past a segmented field's total T repeat the delivery: id h samples the segment of
+    h mod T with its own random stream.  Exactly (fixed point): ids from T + c0 give the image
+    of a one-segment field with the second segment's aperture over the same ids, ids from 2T
+    that of the first segment's; the field's ids [0, 2T) in one call give the image of two
+    calls, one per delivery; and the second delivery is not a copy of the first."""
+    cfg = synth.coupled_hetero_small()
+    ap = cfg["source"]["aperture"]
+    n_pairs = ap["a"].shape[1]
+    a2, b2 = ap["a"].copy(), ap["b"].copy()
+    a2[0, : n_pairs // 2] = 0.0          # the second segment: the field's lower half only
+    b2[0, : n_pairs // 2] = 0.0
+    c0, c1 = 200_000, 100_000
+    T = c0 + c1
+    two = copy.deepcopy(cfg)
+    two["source"]["aperture"] = dict(ap, a=np.concatenate([ap["a"], a2]), b=np.concatenate([ap["b"], b2]),
+                                     counts=np.array([c0, c1], np.uint64))
+
+    def single(a, b):
+        c = copy.deepcopy(cfg)
+        c["source"]["aperture"] = dict(ap, a=a, b=b, counts=np.array([0], np.uint64))
+        return c
+
+    def image(c, runs, batches=4):
+        eng = E.Engine(0, seed=19).configure(c, tally=1, batches=batches, max_chunk=1 << 17)
+        eng.bind()
+        for first, n in runs:
+            eng.run(n, first=first)
+        return eng.image()[0].cpu().numpy()
+
+    n = 50_000
+    m = image(two, [(T + c0, n)])
+    assert m.sum() > 0
+    np.testing.assert_array_equal(m, image(single(a2, b2), [(T + c0, n)]))
+    np.testing.assert_array_equal(image(two, [(2 * T, n)]), image(single(ap["a"], ap["b"]), [(2 * T, n)]))
+    whole = image(two, [(0, 2 * T)])
+    np.testing.assert_array_equal(whole, image(two, [(0, T), (T, T)]))
+    d1, d2 = image(two, [(0, T)]), image(two, [(T, T)])
+    assert not np.array_equal(d1, d2)
+    assert abs(d2.sum() / d1.sum() - 1.0) < 0.05
+
+
 def test_bench_configuration_energy_ledger(E):
     """The benchmark's launch configuration: the full coupled workload, 1e8 histories as one
     2^27-history chunk, 64 batches, with the per-history energy ledger on: every history
