@@ -615,23 +615,30 @@ __global__ void k_img_sum(const double *img, long long hw, int nb, double *part)
     if (threadIdx.x == 0) part[im * nb + blockIdx.x] = sh[0];
 }
 
-// scale of image i: its mean (1 for an image whose mean is not positive)
-__global__ void k_img_scale(const double *part, int nb, long long hw, int n, double *s)
+// Scale of image blockIdx.y (its mean; 1 for an image whose mean is not positive) from the
+// partial sums, added in a fixed tree order; then the batch's 8-channel BF16 input, FP32
+// image channel and target.  Block (0, i) also stores image i's scale for the head.
+__global__ __launch_bounds__(WG) void k_prepare(const double *noisy, const double *thick, const double *target,
+                                                const double *part, int nb, long long hw, uint16_t *x, float *x0,
+                                                float *tgt, double *scale)
 {
-    const int im = blockIdx.x * blockDim.x + threadIdx.x;
-    if (im >= n) return;
+    __shared__ double sh[WG];
+    const int im = blockIdx.y;
     double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += part[im * nb + b];
-    const double m = t / (double)hw;
-    s[im] = m > 0.0 ? m : 1.0;
-}
-
-__global__ void k_prepare(const double *noisy, const double *thick, const double *target, const double *s,
-                          long long hw, long long P, uint16_t *x, float *x0, float *tgt)
-{
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const double inv = 1.0 / s[p / hw];
+    for (int b = threadIdx.x; b < nb; b += WG) t += part[(long long)im * nb + b];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int k = WG / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double m = sh[0] / (double)hw;
+    const double sc = m > 0.0 ? m : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) scale[im] = sc;
+    const long long q = (long long)blockIdx.x * WG + threadIdx.x;
+    if (q >= hw) return;
+    const long long p = (long long)im * hw + q;
+    const double inv = 1.0 / sc;
     const double v = noisy[p] * inv;
     u32x4 o = {pack((float)v, (float)(thick[p] * (1.0 / 20.0))), 0u, 0u, 0u};
     *(u32x4 *)(x + p * 8) = o;
@@ -1002,7 +1009,7 @@ static size_t plan(epidmc_unet *u, int n, int h, int w)
     take(y.x0, P(0) * 4);
     take(y.tgt, P(0) * 4);
     take(y.scale, (size_t)n * 8);
-    u->sum_nb = 64;
+    u->sum_nb = 512;
     take(y.sumpart, (size_t)n * u->sum_nb * 8);
     u->head_blocks = (long long)((P(0) + WG - 1) / WG);
     take(y.headpart, (size_t)u->head_blocks * (HC + 2) * 4);
@@ -1058,12 +1065,11 @@ static hipError_t prepare(epidmc_unet *u, const double *noisy, const double *thi
 {
     auto &y = u->lay;
     const long long hw = (long long)u->h * u->w, P = hw * n;
+    (void)P;
     hipLaunchKernelGGL(k_img_sum, dim3(u->sum_nb, n), dim3(WG), 0, s, noisy, hw, u->sum_nb, at<double>(u, y.sumpart));
-    hipLaunchKernelGGL(k_img_scale, dim3(nblocks(n, 64)), dim3(64), 0, s, (const double *)at<double>(u, y.sumpart),
-                       u->sum_nb, hw, n, at<double>(u, y.scale));
-    hipLaunchKernelGGL(k_prepare, dim3(nblocks(P)), dim3(WG), 0, s, noisy, thick, target,
-                       (const double *)at<double>(u, y.scale), hw, P, at<uint16_t>(u, y.X), at<float>(u, y.x0),
-                       at<float>(u, y.tgt));
+    hipLaunchKernelGGL(k_prepare, dim3(nblocks(hw), n), dim3(WG), 0, s, noisy, thick, target,
+                       (const double *)at<double>(u, y.sumpart), u->sum_nb, hw, at<uint16_t>(u, y.X),
+                       at<float>(u, y.x0), at<float>(u, y.tgt), at<double>(u, y.scale));
     return hipGetLastError();
 }
 
