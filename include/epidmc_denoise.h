@@ -23,7 +23,9 @@
  *
  * Layout: activations are NHWC (image, row, column, channel) with a channel stride `ld`
  * (elements between consecutive pixels), so a tensor can be a channel slice of a wider
- * one.  Convolution weights are [c_out][k][k][c_in].  BF16 values are passed as their
+ * one; the kernels move 8 channels (16 bytes) at a time, so tensor pointers are 16-byte
+ * aligned (a slice starts at a multiple of 8 channels).  Convolution weights are
+ * [c_out][k][k][c_in].  BF16 values are passed as their
  * 16-bit patterns (uint16_t).  All pointers are device pointers unless stated; every
  * call is asynchronous on `stream` (a hipStream_t as void*, NULL = default stream) and
  * allocates no device memory: scratch buffers come from the caller.  Errors: epidmc_status

@@ -275,6 +275,13 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
         }
         __syncthreads();
     }
+    // Epilogue through LDS (the staging buffers are free after the last barrier): each wave
+    // writes its 64-pixel x NT*16-channel tile of BF16 outputs (bias, ReLU and gate applied)
+    // pixel-major, then reads it back as 16-byte runs of 8 channels, so that every global
+    // store writes 8 consecutive NHWC channels instead of one.  Wave-local pixel P = m*16 +
+    // grp*4 + r lies at row P / 32 and column P % 32 of the wave's two rows.
+    constexpr int EP = NT * 16 + 8;   // bf16 per staged pixel (80 or 144 bytes)
+    uint16_t *E = (NT == 4 ? Ws : Xs) + wave * 64 * EP;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int co = co0 + t * 16 + row;
@@ -283,38 +290,53 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int y = ty0 + 2 * wave + (m >> 1), x = tx0 + (m & 1) * 16 + grp * 4 + r;
-                if (y >= a.h || x >= a.wd) continue;
-                const long long p = ibase + (long long)y * a.wd + x;
                 float v = acc[m][t][r] + b;
                 if (a.relu) v = fmaxf(v, 0.0f);
-                if (a.gate && !(bf2f(a.gate[p * a.ldg + co]) > 0.0f)) v = 0.0f;
-                a.y[p * a.ldy + co] = f2bf(v);
-            }
-        if (a.pool) {
-            // the 2 x 2 average of the stored (BF16) outputs, added in the order of a separate
-            // pooling pass: a wave's two rows are one pooled row, and a lane holds both
-            // columns of each pair (r = 0, 1 and 2, 3) in both rows (m and m + 2)
-            const int y = ty0 + 2 * wave;
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-                for (int rp = 0; rp < 2; ++rp) {
-                    const int x = tx0 + hh * 16 + grp * 4 + 2 * rp;
-                    if (y >= a.h || x >= a.wd) continue;
-                    float s = 0.0f;
-                    const int ms[2] = {hh, hh + 2};
-#pragma unroll
-                    for (int i = 0; i < 2; ++i)
-#pragma unroll
-                        for (int j = 0; j < 2; ++j) {
-                            float v = acc[ms[i]][t][2 * rp + j] + b;
-                            if (a.relu) v = fmaxf(v, 0.0f);
-                            s += bf2f(f2bf(v));
-                        }
-                    const long long q = ((long long)img * (a.h / 2) + y / 2) * (a.wd / 2) + x / 2;
-                    a.pool[q * a.ldp + co] = f2bf(0.25f * s);
+                if (a.gate) {
+                    const int y = ty0 + 2 * wave + (m >> 1), x = tx0 + (m & 1) * 16 + grp * 4 + r;
+                    const bool in = y < a.h && x < a.wd;
+                    const long long pg = ibase + (long long)(in ? y : 0) * a.wd + (in ? x : 0);
+                    if (in && !(bf2f(a.gate[pg * a.ldg + co]) > 0.0f)) v = 0.0f;
                 }
+                E[(m * 16 + grp * 4 + r) * EP + t * 16 + row] = f2bf(v);
+            }
+    }
+    __syncthreads();
+    constexpr int CG = NT * 2;   // 8-channel groups per pixel
+#pragma unroll
+    for (int k = 0; k < CG; ++k) {
+        const int j = k * 64 + lane, P = j / CG, c8 = j % CG;
+        const int y = ty0 + 2 * wave + (P >> 5), x = tx0 + (P & 31);
+        if (y >= a.h || x >= a.wd) continue;
+        const long long pg = ibase + (long long)y * a.wd + x;
+        *(u32x4 *)(a.y + pg * a.ldy + co0 + c8 * 8) = *(const u32x4 *)(E + P * EP + c8 * 8);
+    }
+    if (a.pool) {
+        // the 2 x 2 average of the stored (BF16) outputs, added in the order of a separate
+        // pooling pass: the wave's two rows are one pooled row of 16 pixels
+        const int y = ty0 + 2 * wave;
+#pragma unroll
+        for (int k = 0; k < (16 * CG + 63) / 64; ++k) {
+            const int j = k * 64 + lane;
+            if (j >= 16 * CG) break;
+            const int px = j / CG, c8 = j % CG;
+            const int x = tx0 + 2 * px;
+            if (y >= a.h || x >= a.wd) continue;
+            u32x4 w4[4];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) w4[2 * i + jj] = *(const u32x4 *)(E + (i * 32 + 2 * px + jj) * EP + c8 * 8);
+            u32x4 o;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) { s0 += lo(w4[q][w]); s1 += hi(w4[q][w]); }
+                o[w] = pack(0.25f * s0, 0.25f * s1);
+            }
+            const long long q = ((long long)img * (a.h / 2) + y / 2) * (a.wd / 2) + x / 2;
+            *(u32x4 *)(a.pool + q * a.ldp + co0 + c8 * 8) = o;
         }
     }
 }
