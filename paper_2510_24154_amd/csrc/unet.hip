@@ -142,33 +142,14 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A1[m], B1[t], acc[m][t]);
     }
-    // lane holds rows 4*grp + r of each 16-pixel tile, column `row` of each channel tile
-    if (UP) {
-        // each output value goes to its 2 x 2 block of the upsampled image (no gate)
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const long long p = p0 + m * 16 + grp * 4 + r;
-                if (p >= a.P) continue;
-                const int n = (int)(p / hw), rr = (int)(p - (long long)n * hw);
-                const int yi = rr / a.wd, xi = rr - yi * a.wd;
-                const long long q = ((long long)n * 2 * a.h + 2 * yi) * (2 * a.wd) + 2 * xi;
-                const long long q2 = q + 2 * a.wd;
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const int co = co0 + t * 16 + row;
-                    float v = acc[m][t][r] + (a.bias ? a.bias[co] : 0.0f);
-                    if (a.relu) v = fmaxf(v, 0.0f);
-                    const uint16_t o = f2bf(v);
-                    a.y[q * a.ldy + co] = o;
-                    a.y[(q + 1) * a.ldy + co] = o;
-                    a.y[q2 * a.ldy + co] = o;
-                    a.y[(q2 + 1) * a.ldy + co] = o;
-                }
-            }
-        return;
-    }
+    // Epilogue through LDS: the wave's MT*16-pixel x NT*16-channel tile of BF16 outputs
+    // (bias, ReLU and gate applied; lane (row, grp) holds pixels 4*grp + r of each 16-pixel
+    // tile, channel `row` of each channel tile) is written pixel-major and read back as
+    // 16-byte runs of 8 channels, so that every global store writes 8 consecutive NHWC
+    // channels (four of them, the 2 x 2 block, with UP).
+    constexpr int EP = NT * 16 + 8;   // bf16 per staged pixel
+    __shared__ __align__(16) uint16_t Es[4 * 16 * MT * EP];
+    uint16_t *E = Es + wave * 16 * MT * EP;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int co = co0 + t * 16 + row;
@@ -177,13 +158,36 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
         for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const long long p = p0 + m * 16 + grp * 4 + r;
-                if (p >= a.P) continue;
                 float v = acc[m][t][r] + b;
                 if (a.relu) v = fmaxf(v, 0.0f);
-                if (a.gate && !(bf2f(a.gate[p * a.ldg + co]) > 0.0f)) v = 0.0f;
-                a.y[p * a.ldy + co] = f2bf(v);
+                if (!UP && a.gate) {
+                    const long long p = p0 + m * 16 + grp * 4 + r;
+                    if (p < a.P && !(bf2f(a.gate[p * a.ldg + co]) > 0.0f)) v = 0.0f;
+                }
+                E[(m * 16 + grp * 4 + r) * EP + t * 16 + row] = f2bf(v);
             }
+    }
+    __syncthreads();
+    constexpr int CG = NT * 2;   // 8-channel groups per pixel
+#pragma unroll
+    for (int k = 0; k < (16 * MT * CG + 63) / 64; ++k) {
+        const int j = k * 64 + lane;
+        const int P = j / CG, c8 = j % CG;
+        const long long p = p0 + P;
+        if (P >= 16 * MT || p >= a.P) continue;
+        const u32x4 v = *(const u32x4 *)(E + P * EP + c8 * 8);
+        if (UP) {
+            const int n = (int)(p / hw), rr = (int)(p - (long long)n * hw);
+            const int yi = rr / a.wd, xi = rr - yi * a.wd;
+            const long long q = ((long long)n * 2 * a.h + 2 * yi) * (2 * a.wd) + 2 * xi, q2 = q + 2 * a.wd;
+            uint16_t *d = a.y + co0 + c8 * 8;
+            *(u32x4 *)(d + q * a.ldy) = v;
+            *(u32x4 *)(d + (q + 1) * a.ldy) = v;
+            *(u32x4 *)(d + q2 * a.ldy) = v;
+            *(u32x4 *)(d + (q2 + 1) * a.ldy) = v;
+        } else {
+            *(u32x4 *)(a.y + p * a.ldy + co0 + c8 * 8) = v;
+        }
     }
 }
 
