@@ -48,6 +48,18 @@ __device__ __forceinline__ float lo(uint32_t w) { return __uint_as_float(w << 16
 __device__ __forceinline__ float hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 __device__ __forceinline__ uint32_t pack(float a, float b) { return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16); }
 
+// 8 BF16 values with every one whose gate element is not > 0 set to +0 (the ReLU derivative
+// of a backward-data pass)
+__device__ __forceinline__ u32x4 gated(u32x4 v, u32x4 g)
+{
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t keep = (lo(g[w]) > 0.0f ? 0x0000FFFFu : 0u) | (hi(g[w]) > 0.0f ? 0xFFFF0000u : 0u);
+        v[w] &= keep;
+    }
+    return v;
+}
+
 __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
@@ -160,10 +172,6 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
             for (int r = 0; r < 4; ++r) {
                 float v = acc[m][t][r] + b;
                 if (a.relu) v = fmaxf(v, 0.0f);
-                if (!UP && a.gate) {
-                    const long long p = p0 + m * 16 + grp * 4 + r;
-                    if (p < a.P && !(bf2f(a.gate[p * a.ldg + co]) > 0.0f)) v = 0.0f;
-                }
                 E[(m * 16 + grp * 4 + r) * EP + t * 16 + row] = f2bf(v);
             }
     }
@@ -186,7 +194,8 @@ __global__ __launch_bounds__(WG) void k_conv(ConvArgs a)
             *(u32x4 *)(d + q2 * a.ldy) = v;
             *(u32x4 *)(d + (q2 + 1) * a.ldy) = v;
         } else {
-            *(u32x4 *)(a.y + p * a.ldy + co0 + c8 * 8) = v;
+            *(u32x4 *)(a.y + p * a.ldy + co0 + c8 * 8) =
+                a.gate ? gated(v, *(const u32x4 *)(a.gate + p * a.ldg + co0 + c8 * 8)) : v;
         }
     }
 }
@@ -296,12 +305,6 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
             for (int r = 0; r < 4; ++r) {
                 float v = acc[m][t][r] + b;
                 if (a.relu) v = fmaxf(v, 0.0f);
-                if (a.gate) {
-                    const int y = ty0 + 2 * wave + (m >> 1), x = tx0 + (m & 1) * 16 + grp * 4 + r;
-                    const bool in = y < a.h && x < a.wd;
-                    const long long pg = ibase + (long long)(in ? y : 0) * a.wd + (in ? x : 0);
-                    if (in && !(bf2f(a.gate[pg * a.ldg + co]) > 0.0f)) v = 0.0f;
-                }
                 E[(m * 16 + grp * 4 + r) * EP + t * 16 + row] = f2bf(v);
             }
     }
@@ -313,7 +316,9 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
         const int y = ty0 + 2 * wave + (P >> 5), x = tx0 + (P & 31);
         if (y >= a.h || x >= a.wd) continue;
         const long long pg = ibase + (long long)y * a.wd + x;
-        *(u32x4 *)(a.y + pg * a.ldy + co0 + c8 * 8) = *(const u32x4 *)(E + P * EP + c8 * 8);
+        u32x4 v = *(const u32x4 *)(E + P * EP + c8 * 8);
+        if (a.gate) v = gated(v, *(const u32x4 *)(a.gate + pg * a.ldg + co0 + c8 * 8));
+        *(u32x4 *)(a.y + pg * a.ldy + co0 + c8 * 8) = v;
     }
     if (a.pool) {
         // the 2 x 2 average of the stored (BF16) outputs, added in the order of a separate
