@@ -369,6 +369,35 @@ def test_run_until_stops_at_target(E):
     assert eng.sigma_bar(0.5) == pytest.approx(sb)
 
 
+def test_run_until_repeats_a_segmented_field(E):
+    """run_until on a segmented field steps whole deliveries, with history ids continuing
+    past the field's total (new, independent deliveries), until sigma-bar reaches half of one
+    delivery's: it stops on a whole number of deliveries, at least 2 and no more than the 1/N
+    law with the selection bias of a noisy first image allows."""
+    cfg = synth.imrt_field(shape=(64, 64, 32), spacing=0.8, npx=(48, 64), pitch=0.624)
+    cfg = synth.with_histories_scaled(cfg, 500_000)
+    tot = int(cfg["source"]["aperture"]["counts"].sum())
+    eng = E.Engine(0, seed=23).configure(cfg, tally=1, batches=16, max_chunk=1 << 19)
+    eng.bind()
+    eng.run(tot)
+    sb1 = eng.sigma_bar(0.5)
+    eng.reset()
+    done, sb = eng.run_until(0.5 * sb1, thr=0.5, first=0, step=tot, max_hist=40 * tot)
+    print("one delivery", sb1, "run-until", done // tot, "deliveries, sigma-bar", sb)
+    assert sb <= 0.5 * sb1 and done % tot == 0 and 2 <= done // tot < 40
+    assert eng.sigma_bar(0.5) == pytest.approx(sb)
+
+
+def test_kahan_mode_at_the_benchmark_size(E):
+    """The Kahan tally on the full coupled workload (1024 x 768 pixels of 0.39 mm, 2e7
+    histories in one chunk) gives the FP64 tally's image to FP32 rounding."""
+    cfg = synth.coupled_hetero()
+    m0, _, _ = gpu_image(E, cfg, 20_000_000, seed=29, tally=0, batches=8, max_chunk=1 << 25)
+    m2, _, eng = gpu_image(E, cfg, 20_000_000, seed=29, tally=2, batches=8, max_chunk=1 << 25)
+    assert m0.sum() > 0 and eng.counters()["error_word"] == 0
+    np.testing.assert_allclose(m2, m0, rtol=2e-6, atol=1e-13)
+
+
 def test_autotuner_times_the_candidates_that_fit(E):
     from paper_2510_24154_amd.autotune import tune_chunk
     cfg = synth.coupled_hetero_small()
