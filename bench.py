@@ -490,10 +490,11 @@ def parse():
                     help="histories per step (default: the workload's; a segmented field is rescaled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
-    ap.add_argument("--graph", action="store_true",
-                    help="also time the segmented field replayed from one captured HIP graph")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick the history chunk size by timing the candidates that fit (instead of 2^27)")
+    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the segmented field replayed from one captured HIP graph (default on)")
+    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=True,
+                    help="pick chunk size, items per lane and pass mode by timing the candidates that fit "
+                         "(default on; --no-autotune: 2^27, 2, host-driven)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--no-denoiser", action="store_true",
