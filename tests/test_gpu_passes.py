@@ -43,7 +43,7 @@ def test_device_driven_passes_give_the_host_driven_image(E):
     ref.run(n)
     m0, v0 = image(ref)
     assert m0.sum() > 0
-    for dp, ipl in ((1, 2), (3, 2), (24, 2), (-1, 2), (-1, 1), (-1, 8)):
+    for dp, ipl in ((0, 4), (1, 2), (3, 2), (24, 2), (-1, 2), (-1, 1), (-1, 4), (-1, 8)):
         print("device passes", dp, "items per lane", ipl, flush=True)
         eng = engine(E, cfg)
         eng.set_passes(dp, ipl)
