@@ -478,11 +478,13 @@ def test_ids_past_the_total_deliver_the_field_again(E):
 
 def test_bench_configuration_energy_ledger(E):
     """The benchmark's launch configuration: the full coupled workload, 1e8 histories as one
-    2^27-history chunk, 64 batches, with the per-history energy ledger on: every history
-    closes to 1e-9 and the image is finite."""
+    2^27-history chunk, 64 batches, host-driven passes with 4 items per lane (the launch
+    tuner's pick), with the per-history energy ledger on: every history closes to 1e-9 and
+    the image is finite."""
     cfg = synth.coupled_hetero()
     eng = E.Engine(0, seed=1).configure(cfg, batches=64, max_chunk=1 << 27, diag=True)
     eng.bind()
+    eng.set_passes(0, 4)
     eng.run(100_000_000)
     c = eng.counters()
     print("bench configuration: ledger", c["max_ledger_resid"], "woodcock/history", c["woodcock_steps"] / 1e8)
