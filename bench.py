@@ -96,6 +96,26 @@ DN_FLOP = 0.2136e12   # forward FLOPs of the network per 1024 x 768 image (2 x m
 BF16_PEAK = 2.5e15    # dense BF16 MFMA, MI355X
 
 
+def dn_hbm_bytes(px=1024 * 768):
+    """Compulsory HBM bytes of one forward pass over `px` pixels: each layer's input read and
+    output written once (BF16 NHWC, c_l = 32 * 2^l channels at 1/4^l of the pixels), the
+    pooled and upsampled tensors, the 8-channel input (16 B per pixel) built from the two FP64
+    planes, the frame sum, and the head (32-channel read, FP32 image channel, FP64 output)."""
+    P = lambda l: px // 4 ** l
+    c = lambda l: 32 * 2 ** l
+    b = px * 8 + px * (8 + 8 + 16 + 4)
+    for l in range(4):
+        b += (px * 16 if l == 0 else P(l) * c(l - 1) * 2) + P(l) * c(l) * 2
+        b += 2 * P(l) * c(l) * 2 + (P(l + 1) * c(l) * 2 if l < 3 else 0)
+    for l in (2, 1, 0):
+        b += P(l + 1) * c(l + 1) * 2 + P(l) * c(l) * 2
+        b += P(l) * 2 * c(l) * 2 + P(l) * c(l) * 2 + 2 * P(l) * c(l) * 2
+    return b + px * (32 * 2 + 4 + 8)
+
+
+DN_HBM_BYTES = dn_hbm_bytes()   # 1.007e9 for 1024 x 768
+
+
 def error_regions(ref, evl, gmap, sel):
     """Where an image's error sits, against the reference on the same binned grid: the ratio of
     the in-field sums (a global scale error), and the mean signed relative error, the relative
@@ -344,8 +364,14 @@ def denoiser_section(a, E, torch):
         graph.replay()
     sync()
     out["inference_graph_ms"] = round((time.perf_counter() - t) / 20 * 1e3, 3)
-    out["roofline"] = {"bound": "mfma", "achieved": round(DN_FLOP / (f_ms * 1e-3) / 1e12, 1), "peak": 2500.0,
-                       "unit": "TFLOP/s", "frac": round(DN_FLOP / (f_ms * 1e-3) / BF16_PEAK, 4),
+    # the pass does 0.2136 TFLOP on about 1.0 GB of compulsory HBM traffic (every layer's input
+    # and output once, BF16 NHWC), 212 FLOP/B, under the machine balance of 2.5 PFLOP/s over
+    # 8 TB/s (312 FLOP/B): its roofline is the memory one, and the MFMA fraction is also given
+    gbps = DN_HBM_BYTES / (f_ms * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(gbps, 1), "peak": 8000.0, "unit": "GB/s",
+                       "frac": round(gbps / 8000.0, 4), "algorithmic_bytes": DN_HBM_BYTES,
+                       "mfma_TFLOPs": round(DN_FLOP / (f_ms * 1e-3) / 1e12, 1),
+                       "mfma_frac": round(DN_FLOP / (f_ms * 1e-3) / BF16_PEAK, 4),
                        "scope": "whole forward pass, 1024 x 768, BF16 MFMA"}
     return out
 
