@@ -60,6 +60,24 @@ __device__ __forceinline__ u32x4 gated(u32x4 v, u32x4 g)
     return v;
 }
 
+constexpr int HC = 32;   // head input channels
+
+// the head's correction r = bh + wh . t for one pixel's HC BF16 channels (t, 16-byte aligned)
+__device__ __forceinline__ float head_r(const u32x4 *src, const float *wh, const float *bh)
+{
+    float t[HC];
+#pragma unroll
+    for (int q = 0; q < HC / 8; ++q) {
+        const u32x4 v = src[q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { t[8 * q + 2 * j] = lo(v[j]); t[8 * q + 2 * j + 1] = hi(v[j]); }
+    }
+    float r = bh[0];
+#pragma unroll
+    for (int c = 0; c < HC; ++c) r += wh[c] * t[c];
+    return r;
+}
+
 __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
@@ -77,6 +95,11 @@ struct ConvArgs {
     long long P;             // pixels n * h * w
     int ldx, ldy, ldg, cin, cout, h, wd, relu, ldp;
     int up;                  // k_conv only: y is the 2x nearest-neighbour upsampling (2h x 2w) of the output
+    // k_conv3_lds with c_out = 32 only (inference): instead of storing y, apply the network's
+    // head to it and write the denoised image, img = (x0 + bh + wh . y) * s per pixel
+    const float *head_w, *head_b, *head_x0;
+    const double *head_s;
+    double *head_img;
     int cg_shift, kg_total;  // log2(c_in / 8), k * k * c_in / 8
 };
 
@@ -309,6 +332,17 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
             }
     }
     __syncthreads();
+    if (NT * 16 == HC && a.head_img) {
+        // the head (inference): every lane one pixel of the wave's tile, its HC channels read
+        // from the staged tile; the convolution's own output is not stored
+        const int y = ty0 + 2 * wave + (lane >> 5), x = tx0 + (lane & 31);
+        if (y < a.h && x < a.wd) {
+            const long long pg = ibase + (long long)y * a.wd + x;
+            const float out = a.head_x0[pg] + head_r((const u32x4 *)(E + lane * EP), a.head_w, a.head_b);
+            a.head_img[pg] = (double)out * a.head_s[img];
+        }
+        return;
+    }
     constexpr int CG = NT * 2;   // 8-channel groups per pixel
 #pragma unroll
     for (int k = 0; k < CG; ++k) {
@@ -677,14 +711,12 @@ __global__ __launch_bounds__(WG) void k_prepare(const double *noisy, const doubl
     if (target) tgt[p] = (float)(target[p] * inv);
 }
 
-// per pixel: r = bh + wh . t0[p]; out = x0 + r.  Training (tgt != NULL): squared error,
+// training head, per pixel: r = bh + wh . t0[p]; out = x0 + r; squared error against tgt,
 // dL/dr = 2 (out - tgt) / P, gradient at t0 gated by t0 > 0, and per-block partial sums of
-// the loss, dL/db and dL/dw (34 floats per block).  Inference: out * s to `img`.
-constexpr int HC = 32;   // head input channels
+// the loss, dL/db and dL/dw (34 floats per block).  (Inference applies the same head in the
+// last convolution's epilogue.)
 __global__ __launch_bounds__(WG) void k_head(const uint16_t *t0, const float *wh, const float *bh, const float *x0,
-                                             const float *tgt,
-                                             const double *s, long long hw, long long P, double *img, uint16_t *g0,
-                                             float *part)
+                                             const float *tgt, long long P, uint16_t *g0, float *part)
 {
     __shared__ float red[WG / 64][HC + 2];
     const long long p = (long long)blockIdx.x * WG + threadIdx.x;
@@ -697,14 +729,7 @@ __global__ __launch_bounds__(WG) void k_head(const uint16_t *t0, const float *wh
 #pragma unroll
         for (int j = 0; j < 4; ++j) { t[8 * q + 2 * j] = lo(v[j]); t[8 * q + 2 * j + 1] = hi(v[j]); }
     }
-    float r = bh[0];
-#pragma unroll
-    for (int c = 0; c < HC; ++c) r += wh[c] * t[c];
-    const float out = (live ? x0[p] : 0.0f) + r;
-    if (!tgt) {
-        if (live) img[p] = (double)out * s[p / hw];
-        return;
-    }
+    const float out = (live ? x0[p] : 0.0f) + head_r(src, wh, bh);
     const float d = live ? out - tgt[p] : 0.0f;
     const float gr = 2.0f * d / (float)P;
     if (live) {
@@ -810,16 +835,28 @@ static int n_cu()
     return cache[dev];
 }
 
+// the network's head applied in a convolution's epilogue: img = (x0 + b + w . y) * s[image]
+struct Head {
+    const float *w, *b, *x0;
+    const double *s;
+    double *img;
+};
+
 // y = act(conv(x)); with `pool`, also the 2 x 2 average pooling of y into pool (h and w
 // even, no gate), inside the convolution's epilogue where the LDS-tiled kernel runs, else by
 // a separate pass; with `up` (1 x 1 convolutions, no gate), y is the output upsampled 2x by
-// nearest neighbour, written by the epilogue
+// nearest neighbour, written by the epilogue; with `head` (3 x 3, c_in a multiple of 32,
+// c_out = HC, no gate or pool), y is not stored and the head's image is written instead
 static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_t *w, const float *bias, uint16_t *y,
                               int ldy, int cout, const uint16_t *gate, int ldg, int n, int h, int wd, int k, int relu,
-                              hipStream_t s, uint16_t *pool = nullptr, int ldp = 0, int up = 0)
+                              hipStream_t s, uint16_t *pool = nullptr, int ldp = 0, int up = 0,
+                              const Head *head = nullptr)
 {
     ConvArgs a;
     a.x = x; a.w = w; a.gate = gate; a.bias = bias; a.y = y; a.pool = nullptr;
+    a.head_w = head ? head->w : nullptr; a.head_b = head ? head->b : nullptr;
+    a.head_x0 = head ? head->x0 : nullptr; a.head_s = head ? head->s : nullptr;
+    a.head_img = head ? head->img : nullptr;
     a.P = (long long)n * h * wd;
     a.ldx = ldx; a.ldy = ldy; a.ldg = ldg; a.cin = cin; a.cout = cout; a.h = h; a.wd = wd; a.relu = relu; a.ldp = ldp;
     a.up = up;
@@ -828,6 +865,7 @@ static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_
     if (a.P == 0) return hipSuccess;
     if (pool && (h % 2 || wd % 2 || gate || cout % 8 || up)) return hipErrorInvalidValue;
     if (up && (k != 1 || gate)) return hipErrorInvalidValue;
+    if (head && (k != 3 || cin % 32 || cout != HC || gate || pool || up || !head->img)) return hipErrorInvalidValue;
     bool wide = cout % 64 == 0;
     if (k == 3 && cin % 32 == 0) {
         a.pool = pool;
@@ -1104,7 +1142,10 @@ static hipError_t prepare(epidmc_unet *u, const double *noisy, const double *thi
     return hipGetLastError();
 }
 
-static hipError_t forward(epidmc_unet *u, int n, hipStream_t s)
+// the network's activations for the prepared batch; with `img` (inference), the last
+// convolution applies the head in its epilogue and writes the denoised image there instead
+// of storing its own output
+static hipError_t forward(epidmc_unet *u, int n, hipStream_t s, double *img = nullptr)
 {
     auto &y = u->lay;
     const uint16_t *wf = at<uint16_t>(u, y.wf);
@@ -1135,8 +1176,11 @@ static hipError_t forward(epidmc_unet *u, int n, hipStream_t s)
                              c, nullptr, 0, n, hl / 2, wl / 2, 1, 0, s, nullptr, 0, 1)) != hipSuccess) return e;
         if ((e = launch_conv(at<uint16_t>(u, y.cat[l]), 2 * c, 2 * c, wf + A.ow, th + A.ob, at<uint16_t>(u, y.da[l]),
                              c, c, nullptr, 0, n, hl, wl, 3, 1, s)) != hipSuccess) return e;
+        const Layer &H = u->L[NL - 1];
+        const Head head{th + H.ow, th + H.ob, at<float>(u, y.x0), at<double>(u, y.scale), img};
         if ((e = launch_conv(at<uint16_t>(u, y.da[l]), c, c, wf + B.ow, th + B.ob, at<uint16_t>(u, y.db[l]), c, c,
-                             nullptr, 0, n, hl, wl, 3, 1, s)) != hipSuccess) return e;
+                             nullptr, 0, n, hl, wl, 3, 1, s, nullptr, 0, 0, l == 0 && img ? &head : nullptr)) !=
+            hipSuccess) return e;
     }
     return hipGetLastError();
 }
@@ -1152,8 +1196,8 @@ static hipError_t backward(epidmc_unet *u, int n, double *loss, hipStream_t s)
     const long long hb = nblocks(P);
     hipLaunchKernelGGL(k_head, dim3(hb), dim3(WG), 0, s, (const uint16_t *)at<uint16_t>(u, y.db[0]),
                        (const float *)(at<float>(u, y.theta) + H.ow), (const float *)(at<float>(u, y.theta) + H.ob),
-                       (const float *)at<float>(u, y.x0), (const float *)at<float>(u, y.tgt), (const double *)at<double>(u, y.scale), hw, P,
-                       (double *)nullptr, at<uint16_t>(u, y.gdb[0]), at<float>(u, y.headpart));
+                       (const float *)at<float>(u, y.x0), (const float *)at<float>(u, y.tgt), P,
+                       at<uint16_t>(u, y.gdb[0]), at<float>(u, y.headpart));
     hipLaunchKernelGGL(k_head_reduce, dim3(HC + 2), dim3(WG), 0, s, (const float *)at<float>(u, y.headpart), (int)hb, P,
                        gr + H.ow, gr + H.ob, loss);
     hipError_t e = hipGetLastError();
@@ -1514,15 +1558,7 @@ epidmc_status epidmc_unet_forward(epidmc_unet *u, const double *noisy, const dou
     UCHK(hipSetDevice(u->device));
     hipStream_t s = (hipStream_t)stream;
     UCHK(prepare(u, noisy, thickness, nullptr, n, s));
-    UCHK(forward(u, n, s));
-    const long long hw = (long long)u->h * u->w, P = hw * n;
-    const Layer &H = u->L[NL - 1];
-    hipLaunchKernelGGL(k_head, dim3(nblocks(P)), dim3(WG), 0, s, (const uint16_t *)at<uint16_t>(u, u->lay.db[0]),
-                       (const float *)(at<float>(u, u->lay.theta) + H.ow),
-                       (const float *)(at<float>(u, u->lay.theta) + H.ob), (const float *)at<float>(u, u->lay.x0),
-                       (const float *)nullptr, (const double *)at<double>(u, u->lay.scale), hw, P, out,
-                       (uint16_t *)nullptr, (float *)nullptr);
-    UCHK(hipGetLastError());
+    UCHK(forward(u, n, s, out));
     return EPIDMC_OK;
 }
 
