@@ -49,3 +49,19 @@ def test_profiled_traffic_needs_the_current_sources_and_workload(tmp_path, monke
     assert bench.profiled_traffic("k_electron<phantom>", "coupled") == (None, None)
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "def456")
     assert bench.profiled_traffic("k_photon_phantom", "coupled") == (None, None)
+
+
+def test_committed_traffic_figures_are_per_step_of_one_delivery():
+    """A transport step reads one voxel or table entry at a time: past the L2 that is at most a
+    few 128-byte lines.  A per-step figure far above that means the counters of several
+    deliveries (the time-to-1% extrapolation runs more after the timed one) were divided by the
+    step counts of one."""
+    import glob
+    found = 0
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(f):
+            key, _, val = line.strip().partition(": ")
+            if key.startswith("traffic_bytes_per_unit["):
+                found += 1
+                assert 0.0 < float(val) <= 512.0, (os.path.basename(f), key, val)
+    assert found >= 4
