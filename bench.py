@@ -539,10 +539,13 @@ def parse():
     ap.add_argument("--dn-mixed", type=int, default=1,
                     help="1: every other training field is a thorax-like phantom under a multi-segment field")
     ap.add_argument("--t1-measured", action="store_true",
-                    help="also run the workload until sigma-bar <= 1% and time it (a segmented field is "
+                    help="also run the workload until sigma-bar <= 1%% and time it (a segmented field is "
                          "delivered again with new history ids until then; about 150 s for imrt40)")
+    ap.add_argument("--no-t1-accumulated", action="store_true",
+                    help="skip the time to 1%% from an accumulated image (about 8 s of further deliveries after "
+                         "the timed ones; for profiling runs whose counters should cover the timed work only)")
     ap.add_argument("--no-t1-paper", action="store_true",
-                    help="skip the measured time to 1% at the paper's pixel pitch (imrt40_2p5mm, about 35 s)")
+                    help="skip the measured time to 1%% at the paper's pixel pitch (imrt40_2p5mm, about 35 s)")
     return ap.parse_args()
 
 
@@ -699,17 +702,19 @@ def main():
     # selecting the pixels >= 50% of a noisy image's maximum keeps pixels that fluctuated
     # upwards; K deliveries (about 8 s, new history ids each) bring the noise down to where
     # the selection has settled, and sigma-bar then falls as 1/sqrt(N)
-    eng.set_profiling(False)
-    eng.reset()
-    torch.cuda.synchronize()
-    k_acc = max(1, min(1000, int(round(8.0 / t_n))))
-    ta = time.perf_counter()
-    for k in range(k_acc):
-        eng.run(n_step, first=k * n_step)
-    torch.cuda.synchronize()
-    t_acc = time.perf_counter() - ta
-    sb_acc = eng.sigma_bar(0.5)
-    t1_acc = t_acc * (sb_acc / 0.01) ** 2 if sb_acc > 0 else None
+    k_acc, t_acc, sb_acc, t1_acc = 0, None, None, None
+    if not a.no_t1_accumulated:
+        eng.set_profiling(False)
+        eng.reset()
+        torch.cuda.synchronize()
+        k_acc = max(1, min(1000, int(round(8.0 / t_n))))
+        ta = time.perf_counter()
+        for k in range(k_acc):
+            eng.run(n_step, first=k * n_step)
+        torch.cuda.synchronize()
+        t_acc = time.perf_counter() - ta
+        sb_acc = eng.sigma_bar(0.5)
+        t1_acc = t_acc * (sb_acc / 0.01) ** 2 if sb_acc > 0 else None
 
     measured = None
     if a.t1_measured:
@@ -771,9 +776,9 @@ def main():
                    "first_history": first, "chunk": min(chunk, n_step), "items_per_lane": ipl,
                    "device_passes": dpasses, "autotune": tuned},
         "s_to_1pct_extrapolated": round(t1_acc, 2) if t1_acc else None,
-        "sigma_bar_at_N": round(sb_acc, 5),
-        "N_for_sigma_bar": k_acc * n_step,
-        "s_for_N": round(t_acc, 3),
+        "sigma_bar_at_N": round(sb_acc, 5) if sb_acc is not None else None,
+        "N_for_sigma_bar": k_acc * n_step if k_acc else None,
+        "s_for_N": round(t_acc, 3) if t_acc is not None else None,
         "s_to_1pct_one_delivery": round(t1, 2) if t1 else None,
         "s_to_1pct_one_delivery_smoothed_selection": round(t1_s, 2) if t1_s else None,
         "sigma_bar_one_delivery": round(sb, 5),
