@@ -233,11 +233,18 @@ constexpr int TLH = 8, TLW = 32, PH = TLH + 2, PW = TLW + 2;
 constexpr int XP = 40;          // bf16 per staged pixel (32 channels + pad)
 constexpr int WP = 9 * 32 + 8;  // bf16 per staged output channel (9 taps x 32 + pad)
 
-template <int NT>
+// C8: the 8-channel input layer (c_in = 8, c_out = 32).  The patch holds 16 bytes per pixel
+// and the weights [co][12 taps][8] (taps 9-11 zero); an MFMA's 32-deep K takes 4 taps of 8
+// channels, lane group g tap 4s + g at step s, in the order of the generic kernel.
+constexpr int W8 = 12 * 8 + 8;  // C8: bf16 per staged output channel (12 taps x 8 + pad)
+
+template <int NT, bool C8 = false>
 __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
 {
-    __shared__ __align__(16) uint16_t Xs[PH * PW * XP];
-    __shared__ __align__(16) uint16_t Ws[NT * 16 * WP];
+    static_assert(!C8 || NT == 2, "the 8-channel input layer has 32 output channels");
+    constexpr int XS = C8 ? 4 * 64 * (NT * 16 + 8) : PH * PW * XP;   // C8: sized for the epilogue
+    __shared__ __align__(16) uint16_t Xs[XS];
+    __shared__ __align__(16) uint16_t Ws[C8 ? NT * 16 * W8 : NT * 16 * WP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int row = lane & 15, grp = lane >> 4;
     const int ty0 = (blockIdx.x / tiles_x) * TLH, tx0 = (blockIdx.x % tiles_x) * TLW;
@@ -251,6 +258,42 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const u32x4 zero = {0u, 0u, 0u, 0u};
+    if constexpr (C8) {
+        for (int it = tid; it < PH * PW; it += WG) {
+            const int y = ty0 + it / PW - 1, x = tx0 + it % PW - 1;
+            const bool ok = y >= 0 && y < a.h && x >= 0 && x < a.wd;
+            const long long off = ok ? (ibase + (long long)y * a.wd + x) * a.ldx : 0;
+            const u32x4 v = *(const u32x4 *)(a.x + off);
+            *(u32x4 *)(Xs + it * 8) = ok ? v : zero;
+        }
+        for (int it = tid; it < NT * 16 * 12; it += WG) {
+            const int co = it / 12, tap = it % 12;
+            const long long off = tap < 9 ? (long long)(co0 + co) * kstride + tap * 8 : 0;
+            const u32x4 v = *(const u32x4 *)(a.w + off);
+            *(u32x4 *)(Ws + co * W8 + tap * 8) = tap < 9 ? v : zero;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < 3; ++st) {
+            const int tap = 4 * st + grp;
+            const bool tv = tap < 9;
+            const int dy = tv ? tap / 3 : 0, dx = tv ? tap - (tap / 3) * 3 : 0;
+            u32x4 A[4], B[NT];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int q = (2 * wave + (m >> 1) + dy) * PW + (m & 1) * 16 + row + dx;
+                const u32x4 v = *(const u32x4 *)(Xs + q * 8);
+                A[m] = tv ? v : zero;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) B[t] = *(const u32x4 *)(Ws + (t * 16 + row) * W8 + tap * 8);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+        }
+        __syncthreads();
+    } else {
     // the next step's patch and weights are loaded into registers while the current step's
     // MFMAs run, and stored to LDS after the barrier
     constexpr int XI = PH * PW * 4, XN = (XI + WG - 1) / WG;
@@ -310,6 +353,7 @@ __global__ __launch_bounds__(WG) void k_conv3_lds(ConvArgs a, int tiles_x)
                 for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
         }
         __syncthreads();
+    }
     }
     // Epilogue through LDS (the staging buffers are free after the last barrier): each wave
     // writes its 64-pixel x NT*16-channel tile of BF16 outputs (bias, ReLU and gate applied)
@@ -865,6 +909,12 @@ static hipError_t launch_conv(const uint16_t *x, int ldx, int cin, const uint16_
     if (a.P == 0) return hipSuccess;
     if (pool && (h % 2 || wd % 2 || gate || cout % 8 || up)) return hipErrorInvalidValue;
     if (up && (k != 1 || gate)) return hipErrorInvalidValue;
+    if (k == 3 && cin == 8 && cout == 32 && ldx % 8 == 0 && !head) {
+        a.pool = pool;
+        const int tx = (wd + TLW - 1) / TLW, ty = (h + TLH - 1) / TLH;
+        hipLaunchKernelGGL((k_conv3_lds<2, true>), dim3(tx * ty, n, 1), dim3(WG), 0, s, a, tx);
+        return hipGetLastError();
+    }
     if (head && (k != 3 || cin % 32 || cout != HC || gate || pool || up || !head->img)) return hipErrorInvalidValue;
     bool wide = cout % 64 == 0;
     if (k == 3 && cin % 32 == 0) {
