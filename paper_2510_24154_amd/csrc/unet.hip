@@ -8,9 +8,9 @@
 //   forward / backward-data   rows = pixels, columns = output channels.  3x3 layers with
 //                             c_in a multiple of 32 (k_conv3_lds) stage a pixel tile with
 //                             its halo and the weight slab in LDS per 32-channel step and
-//                             read every operand from there; 1x1 layers and the 8-channel
-//                             input layer (k_conv) load each lane's operands straight from
-//                             memory;
+//                             read every operand from there, the 8-channel input layer
+//                             (k_conv3_lds<2, true>) its whole patch at once; 1x1 layers
+//                             (k_conv) load each lane's operands straight from memory;
 //   backward-weights          rows = output channels, columns = (tap, input channel), the
 //                             reduction runs over pixels, so both operands are staged
 //                             through LDS transposed; pixel chunks give FP32 partials that
