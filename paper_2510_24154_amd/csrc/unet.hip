@@ -624,6 +624,28 @@ __global__ void k_weights(const float *w, int cout, int kk, int cin, uint16_t *w
     if (wb) wb[((long long)c * kk + (kk - 1 - tap)) * cout + o] = v;
 }
 
+// all layers' conversions in one launch: layer j takes blocks [first_block[j], first_block[j+1])
+constexpr int WT_MAX = 24;
+struct WeightTable {
+    int n;
+    int first_block[WT_MAX + 1];
+    long long off[WT_MAX];
+    int cout[WT_MAX], kk[WT_MAX], cin[WT_MAX];
+};
+
+__global__ void k_weights_all(const float *theta, uint16_t *wf, uint16_t *wb, WeightTable t)
+{
+    int j = 0;
+    while (j + 1 < t.n && (int)blockIdx.x >= t.first_block[j + 1]) ++j;
+    const int cout = t.cout[j], kk = t.kk[j], cin = t.cin[j];
+    const long long i = (long long)(blockIdx.x - t.first_block[j]) * blockDim.x + threadIdx.x;
+    if (i >= (long long)cout * kk * cin) return;
+    const int c = (int)(i % cin), tap = (int)((i / cin) % kk), o = (int)(i / ((long long)cin * kk));
+    const uint16_t v = f2bf(theta[t.off[j] + i]);
+    wf[t.off[j] + i] = v;
+    wb[t.off[j] + ((long long)c * kk + (kk - 1 - tap)) * cout + o] = v;
+}
+
 // one thread per (output pixel, 8-channel group)
 __global__ void k_pool(const uint16_t *x, int ldx, uint16_t *y, int ldy, int c, int n, int h, int wd)
 {
@@ -1167,14 +1189,23 @@ static size_t plan(epidmc_unet *u, int n, int h, int w)
 
 template <class T> static T *at(epidmc_unet *u, const Buf &b) { return (T *)(u->ws + b.off); }
 
+// the BF16 forward and transposed weights of every convolution (all but the head), one launch
 static hipError_t weights_all(epidmc_unet *u, hipStream_t s)
 {
+    static_assert(NL - 1 <= WT_MAX, "weight table too small");
+    WeightTable t;
+    t.n = NL - 1;
+    long long blocks = 0;
     for (int j = 0; j < NL - 1; ++j) {
         const Layer &x = u->L[j];
-        const long long cnt = (long long)x.cout * x.k * x.k * x.cin;
-        hipLaunchKernelGGL(k_weights, dim3(nblocks(cnt)), dim3(WG), 0, s, at<float>(u, u->lay.theta) + x.ow, x.cout,
-                           x.k * x.k, x.cin, at<uint16_t>(u, u->lay.wf) + x.ow, at<uint16_t>(u, u->lay.wb) + x.ow);
+        t.first_block[j] = (int)blocks;
+        t.off[j] = x.ow;
+        t.cout[j] = x.cout; t.kk[j] = x.k * x.k; t.cin[j] = x.cin;
+        blocks += nblocks((long long)x.cout * x.k * x.k * x.cin);
     }
+    t.first_block[NL - 1] = (int)blocks;
+    hipLaunchKernelGGL(k_weights_all, dim3((unsigned)blocks), dim3(WG), 0, s, (const float *)at<float>(u, u->lay.theta),
+                       at<uint16_t>(u, u->lay.wf), at<uint16_t>(u, u->lay.wb), t);
     return hipGetLastError();
 }
 
